@@ -1,0 +1,215 @@
+"""TEST INFRASTRUCTURE ONLY: ctypes binding of the FP64 CPU oracle.
+
+The oracle (``kgs_oracle.c``) is a plain sequential double-precision
+implementation of the DP-AVF2 scheme for the periodic Klein-Gordon-Schroedinger
+equations (arXiv 2502.09537, sec. 3-4).  Only ``tests/``, the smoke check in
+``__graft_entry__`` and the CPU-baseline leg of ``bench.py`` may import this
+package; the GPU library never does and shares no code with it.
+
+All arrays are float64, C-contiguous, of shape ``(n,) * dim`` (axis 0
+slowest), and are updated in place.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkgs_oracle.so")
+SOURCE = os.path.join(_HERE, "kgs_oracle.c")
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("n", ctypes.c_int32),
+        ("h", ctypes.c_double),
+        ("kappa1", ctypes.c_double),
+        ("kappa2", ctypes.c_double),
+        ("mu", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+    ]
+
+
+@dataclass(frozen=True)
+class Grid:
+    """Periodic box [lo, hi)^dim with n points per axis and the KGS parameters."""
+
+    dim: int
+    n: int
+    lo: float
+    hi: float
+    kappa1: float = 1.0
+    kappa2: float = 1.0
+    mu: float = 1.0
+    gamma: float = 1.0
+
+    @property
+    def h(self) -> float:
+        return (self.hi - self.lo) / self.n
+
+    @property
+    def shape(self) -> tuple:
+        return (self.n,) * self.dim
+
+    def _c(self) -> _Grid:
+        return _Grid(self.dim, self.n, self.h, self.kappa1, self.kappa2, self.mu, self.gamma)
+
+
+_lib = None
+_DP = ctypes.POINTER(ctypes.c_double)
+_IP = ctypes.POINTER(ctypes.c_int64)
+_GP = ctypes.POINTER(_Grid)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain C, no FMA contraction)."""
+    import subprocess
+
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SOURCE):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.run(
+            ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+             "-o", tmp, SOURCE, "-lm"],
+            check=True,
+        )
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        L.kgso_is_red.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64]
+        L.kgso_is_red.restype = ctypes.c_int32
+        L.kgso_psi_update.argtypes = [_GP, ctypes.c_double, _DP, _DP, _DP, ctypes.c_int64]
+        L.kgso_psi_update.restype = None
+        L.kgso_uv_update.argtypes = [_GP, ctypes.c_double, _DP, _DP, _DP, _DP, ctypes.c_int64]
+        L.kgso_uv_update.restype = None
+        for name in ("kgso_base_half", "kgso_adjoint_half"):
+            f = getattr(L, name)
+            f.argtypes = [_GP, ctypes.c_double, _DP, _DP, _DP, _DP, _IP, ctypes.c_int64]
+            f.restype = None
+        L.kgso_step_order.argtypes = [_GP, ctypes.c_double, _DP, _DP, _DP, _DP, _IP, ctypes.c_int64]
+        L.kgso_step_order.restype = ctypes.c_int
+        L.kgso_checkerboard_order.argtypes = [ctypes.c_int32, ctypes.c_int32, _IP]
+        L.kgso_checkerboard_order.restype = ctypes.c_int64
+        L.kgso_step.argtypes = [_GP, ctypes.c_double, _DP, _DP, _DP, _DP, ctypes.c_int64]
+        L.kgso_step.restype = ctypes.c_int
+        L.kgso_energy.argtypes = [_GP, _DP, _DP, _DP, _DP]
+        L.kgso_energy.restype = ctypes.c_double
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    if a.dtype != np.float64 or not a.flags.c_contiguous:
+        raise TypeError("oracle arrays must be C-contiguous float64")
+    return a.ctypes.data_as(_DP)
+
+
+def _check(grid: Grid, *arrays):
+    for a in arrays:
+        if a.size != grid.n ** grid.dim:
+            raise ValueError("array size does not match the grid")
+
+
+class State:
+    """The four real fields (P, Q, U, V) = (Re psi, Im psi, u, u_t)."""
+
+    def __init__(self, P, Q, U, V):
+        self.P = np.ascontiguousarray(P, dtype=np.float64).copy()
+        self.Q = np.ascontiguousarray(Q, dtype=np.float64).copy()
+        self.U = np.ascontiguousarray(U, dtype=np.float64).copy()
+        self.V = np.ascontiguousarray(V, dtype=np.float64).copy()
+
+    @classmethod
+    def from_fields(cls, psi, u, v):
+        psi = np.asarray(psi)
+        return cls(psi.real, psi.imag, u, v)
+
+    def copy(self) -> "State":
+        return State(self.P, self.Q, self.U, self.V)
+
+    def arrays(self):
+        return self.P, self.Q, self.U, self.V
+
+    @property
+    def psi(self):
+        return self.P + 1j * self.Q
+
+
+def is_red(dim: int, n: int, idx: int) -> bool:
+    return bool(lib().kgso_is_red(dim, n, idx))
+
+
+def checkerboard_order(dim: int, n: int) -> np.ndarray:
+    order = np.empty(n ** dim, dtype=np.int64)
+    lib().kgso_checkerboard_order(dim, n, order.ctypes.data_as(_IP))
+    return order
+
+
+def step(grid: Grid, tau: float, s: State, nsteps: int = 1) -> State:
+    """nsteps DP-AVF2 steps in the checkerboard order, in place."""
+    _check(grid, *s.arrays())
+    g = grid._c()
+    rc = lib().kgso_step(ctypes.byref(g), tau, *map(_ptr, s.arrays()), nsteps)
+    if rc != 0:
+        raise RuntimeError(f"kgso_step failed ({rc})")
+    return s
+
+
+def step_order(grid: Grid, tau: float, s: State, order: np.ndarray, nsteps: int = 1) -> State:
+    """nsteps DP-AVF2 steps for an arbitrary grid-point update order, in place."""
+    _check(grid, *s.arrays())
+    order = np.ascontiguousarray(order, dtype=np.int64)
+    if sorted(order.tolist()) != list(range(grid.n ** grid.dim)):
+        raise ValueError("order must be a permutation of all grid points")
+    g = grid._c()
+    rc = lib().kgso_step_order(ctypes.byref(g), tau, *map(_ptr, s.arrays()),
+                               order.ctypes.data_as(_IP), nsteps)
+    if rc != 0:
+        raise RuntimeError(f"kgso_step_order failed ({rc})")
+    return s
+
+
+def base_half(grid: Grid, tau_half: float, s: State, order: np.ndarray) -> State:
+    order = np.ascontiguousarray(order, dtype=np.int64)
+    g = grid._c()
+    lib().kgso_base_half(ctypes.byref(g), tau_half, *map(_ptr, s.arrays()),
+                         order.ctypes.data_as(_IP), order.size)
+    return s
+
+
+def adjoint_half(grid: Grid, tau_half: float, s: State, order: np.ndarray) -> State:
+    order = np.ascontiguousarray(order, dtype=np.int64)
+    g = grid._c()
+    lib().kgso_adjoint_half(ctypes.byref(g), tau_half, *map(_ptr, s.arrays()),
+                            order.ctypes.data_as(_IP), order.size)
+    return s
+
+
+def psi_update(grid: Grid, tau_half: float, s: State, idx: int) -> State:
+    g = grid._c()
+    lib().kgso_psi_update(ctypes.byref(g), tau_half, _ptr(s.P), _ptr(s.Q), _ptr(s.U), int(idx))
+    return s
+
+
+def uv_update(grid: Grid, tau_half: float, s: State, idx: int) -> State:
+    g = grid._c()
+    lib().kgso_uv_update(ctypes.byref(g), tau_half, _ptr(s.P), _ptr(s.Q), _ptr(s.U), _ptr(s.V),
+                         int(idx))
+    return s
+
+
+def energy(grid: Grid, s: State) -> float:
+    """h^dim times the discrete energy E_h (sec. 2), Neumaier-compensated."""
+    _check(grid, *s.arrays())
+    g = grid._c()
+    return float(lib().kgso_energy(ctypes.byref(g), *map(_ptr, s.arrays())))
