@@ -1,0 +1,132 @@
+"""Benchmark: lattice-point updates/s of the DP-AVF2 hot path on one MI355X.
+
+Default workload: 3-D KGS on [-8,8)^3, n = 256, float64 state, tau = 0.002,
+psi0 = e^{-|x|^2} e^{i(x + 0.5y)}, u0 = 0.5 e^{-|x|^2/2}, v0 = 0, all
+parameters 1.  One benchmark "step" is one DP-AVF2 time step of the whole
+grid (both colour sweeps); the timed region runs exactly --steps of them
+followed by one energy evaluation (the drift report), with the state already
+resident in HBM.  Prints one JSON line.
+
+    python bench.py [--steps 200] [--warmup 20] [--precision fp64|fp32]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+ALGO_BYTES = {"fp64": 64, "fp32": 32}  # read + write (P, Q, U, V) once per point-step
+METRIC = "lattice-point updates/s + % HBM roofline (3D 256³ FP64); served p50/p99"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--kernel", choices=["auto", "sweep", "stream"], default="auto")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2,
+                    help="oracle steps on the full grid for the CPU baseline")
+    return ap.parse_args()
+
+
+def cpu_baseline(problem, steps):
+    """The FP64 oracle, single-threaded, on `steps` steps of the same grid."""
+    import oracle
+
+    g = oracle.Grid(problem.dim, problem.n, problem.lo, problem.hi, problem.kappa1,
+                    problem.kappa2, problem.mu, problem.gamma)
+    s = oracle.State.from_fields(problem.psi, problem.u, problem.v)
+    t0 = time.perf_counter()
+    oracle.step(g, problem.tau, s, steps)
+    dt = time.perf_counter() - t0
+    return {"value": problem.points * steps / dt, "unit": "lattice-point updates/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{problem.dim}-D n={problem.n} same initial data, {steps} DP-AVF2 steps "
+                      f"of the full grid, float64, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2502_09537_amd import kgs, workloads
+
+    prec = workloads.FP32 if args.precision == "fp32" else workloads.FP64
+    p = workloads.config_3d(n=args.n, steps=args.steps, precision=prec)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    sim = kgs.simulation_from_problem(p)
+    if args.kernel != "auto":
+        t = sim.tuning
+        t.kernel = {"sweep": kgs.KGS_KERNEL_SWEEP, "stream": kgs.KGS_KERNEL_STREAM}[args.kernel]
+        sim.tuning = t
+    info = sim.info()
+    launches_per_step = 2  # two colour sweeps per DP-AVF2 step (plus one per run)
+
+    sim.step(args.warmup)
+    sim.sync()
+    e0 = sim.energy()
+
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    sim.step(args.steps)
+    stop.record(stream)
+    e1 = sim.energy()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    kernel_ms = start.elapsed_time(stop)
+    sim.close()
+
+    updates = p.points * args.steps
+    value = updates / wall
+    nlaunch = launches_per_step * args.steps + 1
+    avg_launch_s = kernel_ms / 1e3 / nlaunch
+    # algorithmic bytes of one launch: one colour sweep advances half of the
+    # points by one full step
+    algo_per_launch = ALGO_BYTES[args.precision] * p.points * args.steps / nlaunch
+    achieved = algo_per_launch / avg_launch_s / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "lattice-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32-state/f64-math",
+        "data": "synthetic",
+        "config": {"workload": f"kgs3d n={p.n}^3 box [-8,8)^3 tau={p.tau} "
+                               f"{args.precision} state, {args.steps} DP-AVF2 steps",
+                   "points": p.points, "kernel": int(info.kernel), "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "energy_rel_drift": abs(e1 - e0) / abs(e0),
+        "kernel_ms": kernel_ms,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(workloads.config_3d(n=args.n), args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

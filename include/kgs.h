@@ -1,0 +1,178 @@
+/*
+ * kgs.h -- C ABI of the MI355X (gfx950) DP-AVF2 solver for the periodic
+ * Klein-Gordon-Schroedinger (KGS) equations.
+ *
+ * The equations (sec. 1, eq. kgs) are
+ *     i psi_t + (kappa1/2) Lap psi + gamma u psi = 0,
+ *     u_tt - kappa2 Lap u + mu^2 u - gamma |psi|^2 = 0,
+ * on the periodic box [lo, hi)^dim, dim = 1, 2 or 3, with psi complex and u
+ * real.  They are discretised by central differences on n points per axis,
+ * h = (hi - lo)/n (sec. 2), and advanced in time by DP-AVF2: the symmetric
+ * composition of the dual-partition AVF method and its adjoint, each with
+ * tau/2 (sec. 3.1, eq. dp-comp), with every grid point updated by the
+ * explicit closed form of sec. 4.1 (eq. scheme1 / scheme1-adj) and the
+ * points visited in checkerboard order (sec. 4.2): red points, then blue
+ * points for the base half step; blue, then red for the adjoint half step.
+ * A point is red when the sum of its 1-based indices is odd (Algorithm 3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Arrays.  psi_re, psi_im, u and v_t (= u_t) are float64 arrays of n^dim
+ * elements in C order (axis 0 slowest); element (i0, .., i_{dim-1}) is the
+ * value at x = lo + (i0, .., i_{dim-1}) h, the paper's x_j = a + (j-1)h
+ * re-based to 0 (sec. 2).  The boundary is always float64, whatever the
+ * precision of the stored state.
+ *
+ * Memory kinds.  `mem` is KGS_HOST (ordinary host pointers) or KGS_DEVICE
+ * (device pointers on the handle's GPU, e.g. a PyTorch tensor's data_ptr()).
+ * The caller owns every array it passes; the library copies on entry and
+ * keeps no alias.  The library owns the device state of a handle from
+ * kgs_init until kgs_free.
+ *
+ * Streams.  Every GPU operation of a handle is enqueued on the stream given
+ * at kgs_init (a hipStream_t; NULL is the default stream).  kgs_step only
+ * enqueues and returns; kgs_energy, kgs_read_state (and kgs_sync) wait for
+ * the stream.  A handle is not thread-safe; several handles may share a
+ * stream.
+ *
+ * Errors.  Every function returns a KGS_* status and never aborts.  The
+ * message of the last failure is available from kgs_last_error(handle), or
+ * kgs_last_error(NULL) for failures that happen before a handle exists.
+ */
+#ifndef KGS_H
+#define KGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    KGS_OK = 0,
+    KGS_EINVAL = 1,     /* NULL pointer, dim not 1..3, n < 2, hi <= lo, tau 0 or
+                           non-finite, non-finite parameter, bad enum value   */
+    KGS_EODDN = 2,      /* odd n: with periodic wrap the points 0 and n-1 of an
+                           axis would share a colour and be neighbours, so the
+                           colour classes would not be independent (sec. 4.2) */
+    KGS_ESINGULAR = 3,  /* the constant 2x2 (u, v) matrix is singular or its
+                           inverse is not finite (Algorithm 1, step 3)        */
+    KGS_ENOMEM = 4,     /* device allocation failed or exceeds the limit      */
+    KGS_EDEVICE = 5,    /* a HIP call failed; see kgs_last_error              */
+    KGS_ENONFINITE = 6, /* the energy is NaN or infinite                      */
+};
+
+enum { KGS_FP64 = 0, KGS_FP32 = 1 };   /* precision of the stored state */
+enum { KGS_HOST = 0, KGS_DEVICE = 1 }; /* memory kind of boundary arrays */
+
+typedef struct kgs_sim kgs_sim; /* opaque handle; owns the device state */
+
+typedef struct {
+    int32_t dim;       /* 1, 2 or 3                                           */
+    int32_t n;         /* points per axis, even, >= 2                         */
+    double lo, hi;     /* periodic box [lo, hi)^dim; h = (hi - lo)/n          */
+    double tau;        /* full time step; non-zero and finite (a negative tau
+                          runs the scheme backwards: step(-tau) inverts
+                          step(tau))                                          */
+    double kappa1, kappa2, mu, gamma; /* finite; kappa1 may be negative     */
+    int32_t precision; /* KGS_FP64 or KGS_FP32.  With KGS_FP32 the state is
+                          stored in float32; every point update and the
+                          energy are still computed in float64.              */
+    int32_t reserved;  /* must be 0                                           */
+} kgs_config;
+
+/* Create a simulation from the initial state (psi_re + i psi_im, u, v_t at
+ * time 0, laid out as described above) and return it in *out.  The state is
+ * copied to the GPU in the colour-split layout (kgs_read_state reverses it).
+ * `stream` is a hipStream_t (or NULL) on which all work of the handle runs.
+ * Validates cfg (KGS_EINVAL, KGS_EODDN, KGS_ESINGULAR) before it allocates.
+ * On failure *out is NULL and no memory is held. */
+int kgs_init(const kgs_config *cfg, const double *psi_re, const double *psi_im, const double *u,
+             const double *v_t, int32_t mem, void *stream, kgs_sim **out);
+
+/* Enqueue nsteps DP-AVF2 steps (nsteps >= 0; 0 does nothing).  On return of
+ * the enqueued work the state is at a full-step boundary.  Asynchronous:
+ * returns once the kernels are launched (KGS_EINVAL for nsteps < 0). */
+int kgs_step(kgs_sim *sim, int64_t nsteps);
+
+/* Discrete energy of the current state: h^dim times E_h of sec. 2,
+ *   sum_i [ 1/2 ( kappa1 |grad_h psi|_i^2 + kappa2 |grad_h u|_i^2 + v_i^2
+ *                 + mu^2 u_i^2 ) - gamma |psi_i|^2 u_i ],
+ * with forward differences grad_h, reduced on the GPU in float64 with
+ * compensated (double-double) partial sums in a fixed, deterministic order.
+ * Waits for the stream.  Writes *energy and returns KGS_ENONFINITE if it is
+ * not finite. */
+int kgs_energy(kgs_sim *sim, double *energy);
+
+/* Copy the current state out (float64, layout as above) to host or device
+ * arrays of n^dim elements.  Waits for the stream. */
+int kgs_read_state(kgs_sim *sim, double *psi_re, double *psi_im, double *u, double *v_t,
+                   int32_t mem);
+
+/* Replace the current state (float64 arrays as above); enqueued on the
+ * stream.  Reading the state, writing it back and stepping gives bitwise the
+ * same result as stepping without the round trip (float64 state). */
+int kgs_write_state(kgs_sim *sim, const double *psi_re, const double *psi_im, const double *u,
+                    const double *v_t, int32_t mem);
+
+/* Wait until all work enqueued for the handle has finished. */
+int kgs_sync(kgs_sim *sim);
+
+/* Release the device state.  NULL is accepted.  Waits for the stream. */
+int kgs_free(kgs_sim *sim);
+
+/* Message of the last failure on this handle (or, for NULL, of the last
+ * failure in this thread before a handle existed); never NULL. */
+const char *kgs_last_error(const kgs_sim *sim);
+
+/* Name of a status code; never NULL. */
+const char *kgs_status_string(int status);
+
+/* ------------------------------------------------------------------------
+ * Launch configuration.  Every configuration computes bitwise the same
+ * state (same-colour points are independent, sec. 4.2), so these knobs only
+ * change speed.
+ * ---------------------------------------------------------------------- */
+enum {
+    KGS_KERNEL_AUTO = 0,   /* library's choice for the grid                    */
+    KGS_KERNEL_SWEEP = 1,  /* one launch per colour sweep, one thread per point */
+    KGS_KERNEL_STREAM = 2, /* 3-D only: z-streaming kernel, two colour sweeps
+                              (one full step) per launch, ping-pong buffers    */
+    KGS_KERNEL_RESIDENT = 3, /* 1-D only: whole grid in one workgroup's LDS and
+                                registers, all steps in one launch             */
+};
+
+typedef struct {
+    int32_t kernel;        /* KGS_KERNEL_*                                    */
+    int32_t block;         /* threads per workgroup for KGS_KERNEL_SWEEP (64..1024,
+                              multiple of 64); 0 = default                      */
+    int32_t tile_x;        /* KGS_KERNEL_STREAM: tile width in compressed x    */
+    int32_t tile_y;        /* KGS_KERNEL_STREAM: tile height in y              */
+    int32_t reserved[4];
+} kgs_tuning;
+
+/* Read / replace the launch configuration of a handle (KGS_EINVAL for a
+ * configuration that does not apply to the grid). */
+int kgs_get_tuning(const kgs_sim *sim, kgs_tuning *out);
+int kgs_set_tuning(kgs_sim *sim, const kgs_tuning *t);
+
+/* Sizes of a handle: bytes of device memory it holds and the name of the
+ * kernel family that kgs_step launches. */
+typedef struct {
+    int64_t points;        /* n^dim                                           */
+    int64_t device_bytes;  /* device memory held by the handle                */
+    int32_t kernel;        /* KGS_KERNEL_* in use                             */
+    int32_t precision;
+} kgs_info;
+
+int kgs_get_info(const kgs_sim *sim, kgs_info *out);
+
+/* Device memory in bytes that kgs_init would allocate for cfg (0 for an
+ * invalid cfg); lets a caller admit simulations against a memory budget. */
+int64_t kgs_required_bytes(const kgs_config *cfg);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KGS_H */

@@ -1,0 +1,470 @@
+// Host side of the C ABI declared in include/kgs.h: validation, the
+// per-half-step constants of the explicit point updates, device memory, and
+// the order of kernel launches of a DP-AVF2 step.
+//
+// Compiled by the host compiler (it uses binary128 for one constant), linked
+// with the HIP kernels into libkgs.so.
+#include "kgs.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include <hip/hip_runtime_api.h>
+
+#include "kgs_internal.h"
+
+struct kgs_sim {
+    kgs_config cfg;
+    kgs::Geometry geo;
+    double h;
+    double hd;             // h^dim
+    kgs::Coef coef;        // constants of one half step (tau/2)
+    kgs::EnergyCoef ecoef;
+    void *state = nullptr; // 8 colour-split planes
+    void *state2 = nullptr; // second copy for ping-pong kernels (3-D streaming)
+    size_t plane_bytes = 0;
+    double *partials = nullptr;  // energy partials, then the 2-double result
+    double *host_out = nullptr;  // pinned, 2 doubles
+    hipStream_t stream = nullptr;
+    int device = 0;
+    kgs_tuning tuning;
+    int64_t device_bytes = 0;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(kgs_sim *s, int code, const std::string &msg)
+{
+    if (s)
+        s->err = msg;
+    else
+        g_err = msg;
+    return code;
+}
+
+int hip_fail(kgs_sim *s, hipError_t e, const char *what)
+{
+    std::string msg = std::string(what) + ": " + hipGetErrorName(e) + " (" +
+                      hipGetErrorString(e) + ")";
+    return fail(s, e == hipErrorOutOfMemory ? KGS_ENOMEM : KGS_EDEVICE, msg);
+}
+
+bool finite(double x) { return std::isfinite(x); }
+
+size_t elem_bytes(int precision) { return precision == KGS_FP32 ? 4 : 8; }
+
+// Half-step constants.  The expressions (and their evaluation order) state
+// the coefficients of the explicit scheme of sec. 4.1 with tau replaced by the
+// half step tau' = tau/2 and the 2-D "4" by 2*dim.
+kgs::Coef half_step_coef(const kgs_config &c, double h)
+{
+    const double tau = c.tau / 2.0;
+    kgs::Coef k;
+    k.b = tau * c.kappa1 / (2.0 * h * h);
+    k.a = static_cast<double>(c.dim) * k.b;
+    k.e = tau * c.gamma / 2.0;
+    k.s = tau * c.kappa2 / (h * h);
+    k.beta = static_cast<double>(c.dim) * tau * c.kappa2 / (h * h) + tau * c.mu * c.mu / 2.0;
+    k.t2 = tau / 2.0;
+    k.g = tau * c.gamma;
+    // det of [[1, -t2], [beta, 1]] and its reciprocal to ~1e-32 relative
+    const __float128 det = static_cast<__float128>(1.0) +
+                           static_cast<__float128>(k.beta) * static_cast<__float128>(k.t2);
+    const __float128 inv = static_cast<__float128>(1.0) / det;
+    k.rd_hi = static_cast<double>(inv);
+    k.rd_lo = static_cast<double>(inv - static_cast<__float128>(k.rd_hi));
+    return k;
+}
+
+int validate(const kgs_config *c, std::string &msg)
+{
+    if (!c) {
+        msg = "config is NULL";
+        return KGS_EINVAL;
+    }
+    if (c->dim < 1 || c->dim > 3) {
+        msg = "dim must be 1, 2 or 3";
+        return KGS_EINVAL;
+    }
+    if (c->n < 2) {
+        msg = "n must be >= 2";
+        return KGS_EINVAL;
+    }
+    if (c->n % 2) {
+        msg = "n must be even: with periodic wrap an odd n makes two same-colour points "
+              "neighbours";
+        return KGS_EODDN;
+    }
+    if (!finite(c->lo) || !finite(c->hi) || !(c->hi > c->lo)) {
+        msg = "the box [lo, hi) must be finite with hi > lo";
+        return KGS_EINVAL;
+    }
+    if (!finite(c->tau) || c->tau == 0.0) {
+        msg = "tau must be finite and non-zero";
+        return KGS_EINVAL;
+    }
+    if (!finite(c->kappa1) || !finite(c->kappa2) || !finite(c->mu) || !finite(c->gamma)) {
+        msg = "kappa1, kappa2, mu and gamma must be finite";
+        return KGS_EINVAL;
+    }
+    if (c->precision != KGS_FP64 && c->precision != KGS_FP32) {
+        msg = "precision must be KGS_FP64 or KGS_FP32";
+        return KGS_EINVAL;
+    }
+    if (c->reserved != 0) {
+        msg = "reserved must be 0";
+        return KGS_EINVAL;
+    }
+    // n^dim must be representable with room to spare for byte counts
+    double pts = 1.0;
+    for (int a = 0; a < c->dim; ++a) pts *= c->n;
+    if (pts > 4.0e12) {
+        msg = "grid too large";
+        return KGS_EINVAL;
+    }
+    const double h = (c->hi - c->lo) / c->n;
+    if (!finite(h) || h <= 0.0) {
+        msg = "grid spacing is not a positive finite number";
+        return KGS_EINVAL;
+    }
+    const kgs::Coef k = half_step_coef(*c, h);
+    const double det = 1.0 + k.beta * k.t2;
+    if (!finite(k.b) || !finite(k.a) || !finite(k.s) || !finite(k.beta) || !finite(k.g) ||
+        !finite(k.e)) {
+        msg = "a coefficient of the point update is not finite";
+        return KGS_EINVAL;
+    }
+    if (det == 0.0 || !finite(k.rd_hi) || !finite(k.rd_lo) || !finite(det)) {
+        msg = "the 2x2 (u, v) matrix [[1, -tau/4], [beta, 1]] is singular";
+        return KGS_ESINGULAR;
+    }
+    return KGS_OK;
+}
+
+kgs::Geometry make_geometry(const kgs_config &c)
+{
+    kgs::Geometry g;
+    g.dim = c.dim;
+    g.n = c.n;
+    g.half = c.n / 2;
+    g.rows = 1;
+    for (int a = 1; a < c.dim; ++a) g.rows *= c.n;
+    g.count = g.rows * g.half;
+    g.stride = (g.count + 63) / 64 * 64;  // 256-byte aligned planes in float32
+    return g;
+}
+
+int64_t bytes_for(const kgs_config &c)
+{
+    const kgs::Geometry g = make_geometry(c);
+    const int64_t state = 8 * g.stride * static_cast<int64_t>(elem_bytes(c.precision));
+    const int64_t partials = (2 * kgs::energy_partial_slots() + 2) * 8;
+    return state + partials;
+}
+
+int check_device(kgs_sim *s)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(s, e, "hipGetDevice");
+    if (dev != s->device) {
+        e = hipSetDevice(s->device);
+        if (e != hipSuccess) return hip_fail(s, e, "hipSetDevice");
+    }
+    return KGS_OK;
+}
+
+void free_device(void *p)
+{
+    if (p && hipFree(p) != hipSuccess) {
+        // nothing useful to do: the handle is being torn down
+    }
+}
+
+void release(kgs_sim *s)
+{
+    if (!s) return;
+    free_device(s->state);
+    free_device(s->state2);
+    free_device(s->partials);
+    if (s->host_out && hipHostFree(s->host_out) != hipSuccess) {
+    }
+    s->state = s->state2 = nullptr;
+    s->partials = nullptr;
+    s->host_out = nullptr;
+}
+
+// Copy four float64 boundary arrays into the colour-split state.
+int load_state(kgs_sim *s, const double *P, const double *Q, const double *U, const double *V,
+               int32_t mem)
+{
+    if (!P || !Q || !U || !V) return fail(s, KGS_EINVAL, "state array pointer is NULL");
+    if (mem != KGS_HOST && mem != KGS_DEVICE)
+        return fail(s, KGS_EINVAL, "mem must be KGS_HOST or KGS_DEVICE");
+    const int64_t npts = 2 * s->geo.count;
+    const size_t bytes = static_cast<size_t>(npts) * sizeof(double);
+    hipError_t e;
+    if (mem == KGS_DEVICE) {
+        e = kgs::launch_scatter(s->geo, s->cfg.precision, s->state, P, Q, U, V, s->stream);
+        if (e != hipSuccess) return hip_fail(s, e, "scatter kernel");
+        e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return hip_fail(s, e, "hipStreamSynchronize");
+        return KGS_OK;
+    }
+    double *stage = nullptr;
+    e = hipMalloc(&stage, 4 * bytes);
+    if (e != hipSuccess) return hip_fail(s, e, "hipMalloc (staging)");
+    const double *src[4] = {P, Q, U, V};
+    for (int f = 0; f < 4 && e == hipSuccess; ++f)
+        e = hipMemcpyAsync(stage + f * npts, src[f], bytes, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = kgs::launch_scatter(s->geo, s->cfg.precision, s->state, stage, stage + npts,
+                                stage + 2 * npts, stage + 3 * npts, s->stream);
+    hipError_t e2 = hipStreamSynchronize(s->stream);
+    free_device(stage);
+    if (e != hipSuccess) return hip_fail(s, e, "copy-in / scatter");
+    if (e2 != hipSuccess) return hip_fail(s, e2, "hipStreamSynchronize");
+    return KGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *kgs_status_string(int status)
+{
+    switch (status) {
+    case KGS_OK: return "KGS_OK";
+    case KGS_EINVAL: return "KGS_EINVAL";
+    case KGS_EODDN: return "KGS_EODDN";
+    case KGS_ESINGULAR: return "KGS_ESINGULAR";
+    case KGS_ENOMEM: return "KGS_ENOMEM";
+    case KGS_EDEVICE: return "KGS_EDEVICE";
+    case KGS_ENONFINITE: return "KGS_ENONFINITE";
+    default: return "KGS_UNKNOWN";
+    }
+}
+
+const char *kgs_last_error(const kgs_sim *sim)
+{
+    return sim ? sim->err.c_str() : g_err.c_str();
+}
+
+int64_t kgs_required_bytes(const kgs_config *cfg)
+{
+    std::string msg;
+    if (validate(cfg, msg) != KGS_OK) return 0;
+    return bytes_for(*cfg);
+}
+
+int kgs_init(const kgs_config *cfg, const double *psi_re, const double *psi_im, const double *u,
+             const double *v_t, int32_t mem, void *stream, kgs_sim **out)
+{
+    if (!out) return fail(nullptr, KGS_EINVAL, "out is NULL");
+    *out = nullptr;
+    std::string msg;
+    const int rc = validate(cfg, msg);
+    if (rc != KGS_OK) return fail(nullptr, rc, msg);
+    if (!psi_re || !psi_im || !u || !v_t)
+        return fail(nullptr, KGS_EINVAL, "state array pointer is NULL");
+    if (mem != KGS_HOST && mem != KGS_DEVICE)
+        return fail(nullptr, KGS_EINVAL, "mem must be KGS_HOST or KGS_DEVICE");
+
+    kgs_sim *s = new (std::nothrow) kgs_sim();
+    if (!s) return fail(nullptr, KGS_ENOMEM, "host allocation failed");
+    s->cfg = *cfg;
+    s->geo = make_geometry(*cfg);
+    s->h = (cfg->hi - cfg->lo) / cfg->n;
+    s->hd = 1.0;
+    for (int a = 0; a < cfg->dim; ++a) s->hd *= s->h;
+    s->coef = half_step_coef(*cfg, s->h);
+    s->ecoef.k1_h2 = cfg->kappa1 / (s->h * s->h);
+    s->ecoef.k2_h2 = cfg->kappa2 / (s->h * s->h);
+    s->ecoef.mu2 = cfg->mu * cfg->mu;
+    s->ecoef.gamma = cfg->gamma;
+    s->stream = static_cast<hipStream_t>(stream);
+    std::memset(&s->tuning, 0, sizeof(s->tuning));
+    s->tuning.kernel = KGS_KERNEL_SWEEP;
+    s->tuning.block = 256;
+
+    hipError_t e = hipGetDevice(&s->device);
+    if (e != hipSuccess) {
+        hip_fail(s, e, "hipGetDevice");
+        g_err = s->err;
+        delete s;
+        return KGS_EDEVICE;
+    }
+    s->plane_bytes = static_cast<size_t>(s->geo.stride) * elem_bytes(cfg->precision);
+    const size_t partial_bytes = (2 * kgs::energy_partial_slots() + 2) * sizeof(double);
+    int code = KGS_OK;
+    e = hipMalloc(&s->state, 8 * s->plane_bytes);
+    if (e != hipSuccess) code = hip_fail(s, e, "hipMalloc (state)");
+    if (code == KGS_OK) {
+        e = hipMalloc(reinterpret_cast<void **>(&s->partials), partial_bytes);
+        if (e != hipSuccess) code = hip_fail(s, e, "hipMalloc (energy partials)");
+    }
+    if (code == KGS_OK) {
+        e = hipHostMalloc(reinterpret_cast<void **>(&s->host_out), 2 * sizeof(double),
+                          hipHostMallocDefault);
+        if (e != hipSuccess) code = hip_fail(s, e, "hipHostMalloc");
+    }
+    if (code == KGS_OK) {
+        // padding between planes is never read by a kernel; clear it anyway
+        e = hipMemsetAsync(s->state, 0, 8 * s->plane_bytes, s->stream);
+        if (e != hipSuccess) code = hip_fail(s, e, "hipMemsetAsync");
+    }
+    if (code == KGS_OK) code = load_state(s, psi_re, psi_im, u, v_t, mem);
+    if (code != KGS_OK) {
+        g_err = s->err;
+        release(s);
+        delete s;
+        return code;
+    }
+    s->device_bytes = static_cast<int64_t>(8 * s->plane_bytes + partial_bytes);
+    *out = s;
+    return KGS_OK;
+}
+
+int kgs_step(kgs_sim *s, int64_t nsteps)
+{
+    if (!s) return fail(nullptr, KGS_EINVAL, "handle is NULL");
+    if (nsteps < 0) return fail(s, KGS_EINVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return KGS_OK;
+    int rc = check_device(s);
+    if (rc != KGS_OK) return rc;
+    const int prec = s->cfg.precision;
+    const int block = s->tuning.block > 0 ? s->tuning.block : 256;
+    auto sweep = [&](int kind) {
+        hipError_t e = kgs::launch_sweep(s->geo, prec, s->state, kind, s->coef, block, s->stream);
+        return e == hipSuccess ? KGS_OK : hip_fail(s, e, "sweep kernel launch");
+    };
+    rc = sweep(kgs::PASS_R_BASE);
+    for (int64_t i = 1; i < nsteps && rc == KGS_OK; ++i) {
+        rc = sweep(kgs::PASS_B_FULL);
+        if (rc == KGS_OK) rc = sweep(kgs::PASS_R_ADJ_BASE);
+    }
+    if (rc == KGS_OK) rc = sweep(kgs::PASS_B_FULL);
+    if (rc == KGS_OK) rc = sweep(kgs::PASS_R_ADJ);
+    return rc;
+}
+
+int kgs_energy(kgs_sim *s, double *energy)
+{
+    if (!s || !energy) return fail(s, KGS_EINVAL, "handle or output is NULL");
+    int rc = check_device(s);
+    if (rc != KGS_OK) return rc;
+    double *out = s->partials + 2 * kgs::energy_partial_slots();
+    hipError_t e = kgs::launch_energy(s->geo, s->cfg.precision, s->state, s->ecoef, s->partials,
+                                      out, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "energy kernel launch");
+    e = hipMemcpyAsync(s->host_out, out, 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "hipMemcpyAsync (energy)");
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "hipStreamSynchronize");
+    *energy = s->hd * (s->host_out[0] + s->host_out[1]);
+    if (!std::isfinite(*energy)) return fail(s, KGS_ENONFINITE, "energy is not finite");
+    return KGS_OK;
+}
+
+int kgs_read_state(kgs_sim *s, double *P, double *Q, double *U, double *V, int32_t mem)
+{
+    if (!s) return fail(nullptr, KGS_EINVAL, "handle is NULL");
+    if (!P || !Q || !U || !V) return fail(s, KGS_EINVAL, "state array pointer is NULL");
+    if (mem != KGS_HOST && mem != KGS_DEVICE)
+        return fail(s, KGS_EINVAL, "mem must be KGS_HOST or KGS_DEVICE");
+    int rc = check_device(s);
+    if (rc != KGS_OK) return rc;
+    const int64_t npts = 2 * s->geo.count;
+    const size_t bytes = static_cast<size_t>(npts) * sizeof(double);
+    hipError_t e;
+    if (mem == KGS_DEVICE) {
+        e = kgs::launch_gather(s->geo, s->cfg.precision, s->state, P, Q, U, V, s->stream);
+        if (e != hipSuccess) return hip_fail(s, e, "gather kernel");
+        e = hipStreamSynchronize(s->stream);
+        return e == hipSuccess ? KGS_OK : hip_fail(s, e, "hipStreamSynchronize");
+    }
+    double *stage = nullptr;
+    e = hipMalloc(&stage, 4 * bytes);
+    if (e != hipSuccess) return hip_fail(s, e, "hipMalloc (staging)");
+    e = kgs::launch_gather(s->geo, s->cfg.precision, s->state, stage, stage + npts,
+                           stage + 2 * npts, stage + 3 * npts, s->stream);
+    double *dst[4] = {P, Q, U, V};
+    for (int f = 0; f < 4 && e == hipSuccess; ++f)
+        e = hipMemcpyAsync(dst[f], stage + f * npts, bytes, hipMemcpyDeviceToHost, s->stream);
+    hipError_t e2 = hipStreamSynchronize(s->stream);
+    free_device(stage);
+    if (e != hipSuccess) return hip_fail(s, e, "gather / copy-out");
+    if (e2 != hipSuccess) return hip_fail(s, e2, "hipStreamSynchronize");
+    return KGS_OK;
+}
+
+int kgs_write_state(kgs_sim *s, const double *P, const double *Q, const double *U,
+                    const double *V, int32_t mem)
+{
+    if (!s) return fail(nullptr, KGS_EINVAL, "handle is NULL");
+    int rc = check_device(s);
+    if (rc != KGS_OK) return rc;
+    return load_state(s, P, Q, U, V, mem);
+}
+
+int kgs_sync(kgs_sim *s)
+{
+    if (!s) return fail(nullptr, KGS_EINVAL, "handle is NULL");
+    int rc = check_device(s);
+    if (rc != KGS_OK) return rc;
+    hipError_t e = hipStreamSynchronize(s->stream);
+    return e == hipSuccess ? KGS_OK : hip_fail(s, e, "hipStreamSynchronize");
+}
+
+int kgs_free(kgs_sim *s)
+{
+    if (!s) return KGS_OK;
+    int rc = check_device(s);
+    if (rc == KGS_OK) {
+        hipError_t e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) rc = hip_fail(s, e, "hipStreamSynchronize");
+    }
+    if (rc != KGS_OK) g_err = s->err;
+    release(s);
+    delete s;
+    return rc;
+}
+
+int kgs_get_tuning(const kgs_sim *s, kgs_tuning *out)
+{
+    if (!s || !out) return fail(nullptr, KGS_EINVAL, "handle or output is NULL");
+    *out = s->tuning;
+    return KGS_OK;
+}
+
+int kgs_set_tuning(kgs_sim *s, const kgs_tuning *t)
+{
+    if (!s || !t) return fail(s, KGS_EINVAL, "handle or tuning is NULL");
+    kgs_tuning nt = *t;
+    if (nt.kernel == KGS_KERNEL_AUTO) nt.kernel = KGS_KERNEL_SWEEP;
+    if (nt.kernel != KGS_KERNEL_SWEEP)
+        return fail(s, KGS_EINVAL, "kernel family not available for this grid");
+    if (nt.block == 0) nt.block = 256;
+    if (nt.block < 64 || nt.block > 1024 || nt.block % 64)
+        return fail(s, KGS_EINVAL, "block must be a multiple of 64 in [64, 1024]");
+    s->tuning = nt;
+    return KGS_OK;
+}
+
+int kgs_get_info(const kgs_sim *s, kgs_info *out)
+{
+    if (!s || !out) return fail(nullptr, KGS_EINVAL, "handle or output is NULL");
+    out->points = 2 * s->geo.count;
+    out->device_bytes = s->device_bytes;
+    out->kernel = s->tuning.kernel;
+    out->precision = s->cfg.precision;
+    return KGS_OK;
+}
+
+}  // extern "C"

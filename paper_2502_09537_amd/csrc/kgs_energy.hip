@@ -1,0 +1,198 @@
+// Discrete energy E_h of sec. 2 (without the h^dim factor, which the host
+// applies): a deterministic, compensated float64 reduction.
+//
+// Each thread sums the energy density of its points into a double-double
+// (TwoSum), a wavefront of 64 lanes combines its lanes with shuffles in a
+// fixed tree, the waves of a workgroup combine through LDS in a fixed order,
+// and one final workgroup combines the per-workgroup partials in a fixed
+// order.  The grid size depends only on the problem size, so the result is
+// bitwise reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include "kgs_internal.h"
+
+namespace kgs {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kSlots = 2048;  // maximum number of per-workgroup partials
+
+struct DD {
+    double hi, lo;
+};
+
+__device__ __forceinline__ DD two_sum(double a, double b)
+{
+    const double s = a + b;
+    const double bb = s - a;
+    const double err = (a - (s - bb)) + (b - bb);
+    return {s, err};
+}
+
+__device__ __forceinline__ DD dd_add(DD a, DD b)
+{
+    const DD s = two_sum(a.hi, b.hi);
+    const double lo = s.lo + (a.lo + b.lo);
+    const double hi = s.hi + lo;
+    return {hi, lo - (hi - s.hi)};
+}
+
+__device__ __forceinline__ DD dd_add(DD a, double b)
+{
+    const DD s = two_sum(a.hi, b);
+    const double lo = s.lo + a.lo;
+    const double hi = s.hi + lo;
+    return {hi, lo - (hi - s.hi)};
+}
+
+// Fixed-order tree over the 64 lanes; the result is valid in lane 0.
+__device__ __forceinline__ DD wave_reduce(DD v)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        DD o;
+        o.hi = __shfl_down(v.hi, off, 64);
+        o.lo = __shfl_down(v.lo, off, 64);
+        v = dd_add(v, o);
+    }
+    return v;
+}
+
+// Reduce a workgroup of kBlock threads; the result is valid in thread 0.
+__device__ __forceinline__ DD block_reduce(DD v)
+{
+    __shared__ double s_hi[kBlock / 64], s_lo[kBlock / 64];
+    v = wave_reduce(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        s_hi[wave] = v.hi;
+        s_lo[wave] = v.lo;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        DD acc = {s_hi[0], s_lo[0]};
+        for (int w = 1; w < kBlock / 64; ++w) acc = dd_add(acc, DD{s_hi[w], s_lo[w]});
+        v = acc;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ double ld(const T *p)
+{
+    return static_cast<double>(*p);
+}
+
+// Energy density of the point of colour c at (row, xh), with forward
+// differences to the other colour:
+//   1/2 (k1/h^2 sum_axes (dP^2 + dQ^2) + k2/h^2 sum_axes dU^2 + V^2 + mu^2 U^2)
+//   - gamma (P^2 + Q^2) U.
+template <int DIM, typename T>
+__device__ __forceinline__ double density(const T *__restrict__ base, int64_t stride, int n,
+                                          int c, int64_t row, int xh, const EnergyCoef &k)
+{
+    const int H = n >> 1;
+    int s = 0;
+    int64_t fwd0 = 0, fwd1 = 0;  // rows one step forward along axis 0 and axis 1
+    if (DIM == 2) {
+        const int i0 = static_cast<int>(row);
+        s = i0;
+        fwd0 = i0 == n - 1 ? 0 : i0 + 1;
+    } else if (DIM == 3) {
+        const int i0 = static_cast<int>(row / n);
+        const int i1 = static_cast<int>(row - static_cast<int64_t>(i0) * n);
+        s = i0 + i1;
+        fwd0 = static_cast<int64_t>(i0 == n - 1 ? 0 : i0 + 1) * n + i1;
+        fwd1 = static_cast<int64_t>(i0) * n + (i1 == n - 1 ? 0 : i1 + 1);
+    }
+    const int o = (s + DIM + 1 + c) & 1;
+    int xp = xh + o;
+    if (xp >= H) xp -= H;
+    const T *own = base + static_cast<int64_t>(4 * c) * stride;
+    const T *oth = base + static_cast<int64_t>(4 * (c ^ 1)) * stride;
+    const int64_t i = row * H + xh;
+    const double p = ld(own + F_P * stride + i), q = ld(own + F_Q * stride + i);
+    const double u = ld(own + F_U * stride + i), v = ld(own + F_V * stride + i);
+    double gp = 0.0, gq = 0.0, gu = 0.0;
+    auto add = [&](int64_t j) {
+        const double dp = ld(oth + F_P * stride + j) - p;
+        const double dq = ld(oth + F_Q * stride + j) - q;
+        const double du = ld(oth + F_U * stride + j) - u;
+        gp = gp + dp * dp;
+        gq = gq + dq * dq;
+        gu = gu + du * du;
+    };
+    if (DIM >= 2) add(fwd0 * H + xh);
+    if (DIM == 3) add(fwd1 * H + xh);
+    add(row * H + xp);
+    return 0.5 * (k.k1_h2 * (gp + gq) + k.k2_h2 * gu + v * v + k.mu2 * (u * u)) -
+           k.gamma * (p * p + q * q) * u;
+}
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock)
+energy_partial_kernel(const T *__restrict__ base, int64_t stride, int n, int64_t count,
+                      EnergyCoef k, double *__restrict__ partials)
+{
+    const int H = n >> 1;
+    DD acc = {0.0, 0.0};
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < count;
+         t += static_cast<int64_t>(gridDim.x) * kBlock) {
+        const int64_t row = t / H;
+        const int xh = static_cast<int>(t - row * H);
+        acc = dd_add(acc, density<DIM>(base, stride, n, RED, row, xh, k));
+        acc = dd_add(acc, density<DIM>(base, stride, n, BLUE, row, xh, k));
+    }
+    acc = block_reduce(acc);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = acc.hi;
+        partials[2 * blockIdx.x + 1] = acc.lo;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+energy_final_kernel(const double *__restrict__ partials, int nparts, double *__restrict__ out)
+{
+    DD acc = {0.0, 0.0};
+    for (int i = threadIdx.x; i < nparts; i += kBlock)
+        acc = dd_add(acc, DD{partials[2 * i], partials[2 * i + 1]});
+    acc = block_reduce(acc);
+    if (threadIdx.x == 0) {
+        out[0] = acc.hi;
+        out[1] = acc.lo;
+    }
+}
+
+}  // namespace
+
+int energy_partial_slots() { return kSlots; }
+
+hipError_t launch_energy(const Geometry &g, int precision, const void *state,
+                         const EnergyCoef &k, double *partials, double *out, hipStream_t s)
+{
+    if (!state || !partials || !out || g.dim < 1 || g.dim > 3 || g.n < 2 || (g.n & 1) ||
+        g.count <= 0 || g.stride < g.count)
+        return hipErrorInvalidValue;
+    int64_t blocks = (g.count + kBlock - 1) / kBlock;
+    if (blocks > kSlots) blocks = kSlots;
+    const dim3 grid(static_cast<unsigned>(blocks)), threads(kBlock);
+#define KGS_ENERGY(D, T)                                                                        \
+    hipLaunchKernelGGL((energy_partial_kernel<D, T>), grid, threads, 0, s,                      \
+                       static_cast<const T *>(state), g.stride, g.n, g.count, k, partials)
+    if (precision == 0) {
+        if (g.dim == 1) KGS_ENERGY(1, double);
+        else if (g.dim == 2) KGS_ENERGY(2, double);
+        else KGS_ENERGY(3, double);
+    } else {
+        if (g.dim == 1) KGS_ENERGY(1, float);
+        else if (g.dim == 2) KGS_ENERGY(2, float);
+        else KGS_ENERGY(3, float);
+    }
+#undef KGS_ENERGY
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(kBlock), 0, s, partials,
+                       static_cast<int>(blocks), out);
+    return hipGetLastError();
+}
+
+}  // namespace kgs

@@ -1,0 +1,90 @@
+// Internal interface between the host side of the library (kgs_api.cpp,
+// compiled by the host compiler) and the HIP kernels (*.hip, gfx950).
+//
+// Device layout of a simulation ("colour-split structure of arrays"):
+//   8 planes = 2 colours (0 = red, 1 = blue) x 4 fields (P = Re psi,
+//   Q = Im psi, U = u, V = u_t), plane (colour, field) at
+//   base + (4*colour + field) * stride elements.
+//   Within a plane a point is addressed as row * H + xh, where H = n/2,
+//   row = i0 (2-D) or i0*n + i1 (3-D) or 0 (1-D) enumerates the grid lines
+//   along the last (fastest) axis x, and xh = x/2 is x compressed to the
+//   points of one colour.  In row r with index sum s (i0 + i1 in 3-D, i0 in
+//   2-D, 0 in 1-D) the points of colour c sit at x = 2 xh + o_c with
+//   o_c = (s + dim + 1 + c) & 1: red points have an odd sum of 1-based
+//   indices (Algorithm 3 of the paper).
+//   Consequences used by every kernel: the two x-neighbours of (r, xh, o) in
+//   the other colour are xh - 1 + o and xh + o (mod H); the neighbours along
+//   every other axis sit at the same xh in the neighbouring rows.
+#pragma once
+
+#include <cstdint>
+
+#include <hip/hip_runtime_api.h>
+
+namespace kgs {
+
+enum Colour { RED = 0, BLUE = 1 };
+enum Field { F_P = 0, F_Q = 1, F_U = 2, F_V = 3 };
+
+// Colour-sweep kinds.  A run of K steps is
+//   R_BASE, (B_FULL, R_ADJ_BASE)^(K-1), B_FULL, R_ADJ
+// because blue points do not change between the base and the adjoint blue
+// sweeps, and red points do not change between the adjoint red sweep of a
+// step and the base red sweep of the next (the paper's four masked passes per
+// step, Algorithm 3, fused into two sweeps).
+enum PassKind {
+    PASS_R_BASE = 0,     // red:  psi, then (u,v)                   (base)
+    PASS_B_FULL = 1,     // blue: psi, (u,v) (base); (u,v), psi (adjoint)
+    PASS_R_ADJ = 2,      // red:  (u,v), then psi                   (adjoint)
+    PASS_R_ADJ_BASE = 3, // red:  (u,v), psi (adjoint); psi, (u,v) (next base)
+};
+
+// Per-half-step constants of the explicit point updates, tau' = tau/2.
+// psi:   (i - c) psi' = (i + c) psi - b S,   c = a - e u,
+// (u,v): u' - t2 v' = u + t2 v,  beta u' + v' = v - beta u + s S_u + g |psi|^2.
+struct Coef {
+    double b;      // tau' kappa1 / (2 h^2)
+    double a;      // dim * b
+    double e;      // (tau' gamma) / 2
+    double s;      // tau' kappa2 / h^2
+    double beta;   // dim tau' kappa2 / h^2 + tau' mu^2 / 2
+    double t2;     // tau' / 2
+    double g;      // tau' gamma
+    double rd_hi;  // 1 / (1 + t2 beta) as the unevaluated sum rd_hi + rd_lo
+    double rd_lo;
+};
+
+// Constants of the energy density (multiplied by h^dim on the host).
+struct EnergyCoef {
+    double k1_h2;  // kappa1 / h^2
+    double k2_h2;  // kappa2 / h^2
+    double mu2;    // mu^2
+    double gamma;
+};
+
+struct Geometry {
+    int dim;
+    int n;
+    int half;        // n / 2
+    int64_t rows;    // n^(dim-1)
+    int64_t count;   // points per colour = rows * half
+    int64_t stride;  // elements between planes (count rounded up)
+};
+
+// Kernel launchers (kgs_sweep.hip, kgs_energy.hip).  They check the launch
+// shape against the geometry on the host and return hipErrorInvalidValue
+// rather than launch a kernel whose indexing would not fit.
+hipError_t launch_scatter(const Geometry &g, int precision, void *state, const double *P,
+                          const double *Q, const double *U, const double *V, hipStream_t s);
+hipError_t launch_gather(const Geometry &g, int precision, const void *state, double *P,
+                         double *Q, double *U, double *V, hipStream_t s);
+hipError_t launch_sweep(const Geometry &g, int precision, void *state, int kind, const Coef &k,
+                        int block, hipStream_t s);
+// Writes the double-double sum of the energy density (without h^dim) to
+// out[0] + out[1] (device memory); `partials` holds 2*energy_partial_slots()
+// doubles.
+int energy_partial_slots();
+hipError_t launch_energy(const Geometry &g, int precision, const void *state,
+                         const EnergyCoef &k, double *partials, double *out, hipStream_t s);
+
+}  // namespace kgs

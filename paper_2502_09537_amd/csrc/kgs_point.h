@@ -1,0 +1,71 @@
+// Device-side point updates of the explicit DP-AVF scheme (sec. 4.1 of the
+// paper, eq. scheme1 and scheme1-adj), shared by every sweep kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kgs_internal.h"
+
+namespace kgs {
+
+// Psi at one point, given the neighbour sum S = sr + i si of the 2*dim
+// neighbours and the value u currently held at the point (u^n in the base
+// scheme, u^{n+1} in the adjoint scheme, where (u,v) is solved first):
+//   (i - c) psi' = (i + c) psi - b S,   c = a - e u,
+// i.e. psi' = num (-c - i) / (1 + c^2) with num = (i + c) psi - b S.
+__device__ __forceinline__ void psi_update(const Coef &k, double &pr, double &pi, double u,
+                                           double sr, double si)
+{
+    const double c = k.a - k.e * u;
+    const double nr = c * pr - pi - k.b * sr;
+    const double ni = pr + c * pi - k.b * si;
+    const double inv = 1.0 / (1.0 + c * c);
+    pr = (ni - c * nr) * inv;
+    pi = -(nr + c * ni) * inv;
+}
+
+// (u, v) at one point, given the neighbour sum su of u and the value |psi|^2
+// currently held at the point: the 2x2 system
+//   u' - t2 v' = u + t2 v = r1,   beta u' + v' = v - beta u + s su + g |psi|^2 = r2
+// solved with its constant inverse (1/det) [[1, t2], [-beta, 1]].  1/det is
+// the double-double rd_hi + rd_lo applied with one fused rounding, so the
+// reused constant does not scale every solve by the same rounding error
+// (which would make the energy drift in one direction).
+__device__ __forceinline__ void uv_update(const Coef &k, double pr, double pi, double &u,
+                                          double &v, double su)
+{
+    const double A = pr * pr + pi * pi;
+    const double r1 = u + k.t2 * v;
+    const double r2 = v - k.beta * u + k.s * su + k.g * A;
+    const double xu = r1 + k.t2 * r2;
+    const double xv = r2 - k.beta * r1;
+    u = fma(xu, k.rd_hi, xu * k.rd_lo);
+    v = fma(xv, k.rd_hi, xv * k.rd_lo);
+}
+
+// The point updates of one colour sweep (see PassKind), with the neighbour
+// sums computed once: the other colour does not change within a sweep.
+template <int KIND>
+__device__ __forceinline__ void sweep_point(const Coef &k, double &pr, double &pi, double &u,
+                                            double &v, double sr, double si, double su)
+{
+    if (KIND == PASS_R_BASE) {
+        psi_update(k, pr, pi, u, sr, si);
+        uv_update(k, pr, pi, u, v, su);
+    } else if (KIND == PASS_B_FULL) {
+        psi_update(k, pr, pi, u, sr, si);
+        uv_update(k, pr, pi, u, v, su);
+        uv_update(k, pr, pi, u, v, su);
+        psi_update(k, pr, pi, u, sr, si);
+    } else if (KIND == PASS_R_ADJ) {
+        uv_update(k, pr, pi, u, v, su);
+        psi_update(k, pr, pi, u, sr, si);
+    } else {  // PASS_R_ADJ_BASE
+        uv_update(k, pr, pi, u, v, su);
+        psi_update(k, pr, pi, u, sr, si);
+        psi_update(k, pr, pi, u, sr, si);
+        uv_update(k, pr, pi, u, v, su);
+    }
+}
+
+}  // namespace kgs

@@ -1,0 +1,265 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bars: float64 state <= 1e-12 relative in the max norm per field, float32
+state <= 1e-5; colour sweeps are bitwise independent of the launch shape.
+Every case prints its name before it touches the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_09537_amd import kgs, workloads
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def grid_of(p):
+    return oracle.Grid(p.dim, p.n, p.lo, p.hi, p.kappa1, p.kappa2, p.mu, p.gamma)
+
+
+def oracle_run(p, steps):
+    s = oracle.State.from_fields(p.psi, p.u, p.v)
+    oracle.step(grid_of(p), p.tau, s, steps)
+    return s
+
+
+def gpu_run(p, steps, tuning=None, host=False, chunks=None):
+    sim = kgs.simulation_from_problem(p, host=host, tuning=tuning)
+    try:
+        if chunks:
+            for c in chunks:
+                sim.step(c)
+        else:
+            sim.step(steps)
+        return sim.read_state()
+    finally:
+        sim.close()
+
+
+def rel_errors(gpu, ref):
+    psi, u, v = gpu
+    scale = lambda a: max(float(np.max(np.abs(a))), 1e-300)
+    return (float(np.max(np.abs(psi - ref.psi))) / scale(ref.psi),
+            float(np.max(np.abs(u - ref.U))) / scale(ref.U),
+            float(np.max(np.abs(v - ref.V))) / max(scale(ref.V), scale(ref.U)))
+
+
+def assert_parity(p, steps, tol, **kw):
+    say(p.name, p.dim, p.n, steps, "fp32" if p.precision else "fp64", kw)
+    got = gpu_run(p, steps, **kw)
+    ref = oracle_run(p, steps)
+    errs = rel_errors(got, ref)
+    print("  max-norm relative errors psi/u/v:", errs, flush=True)
+    assert max(errs) <= tol, errs
+    return got, ref
+
+
+# ---------------------------------------------------------------------------
+# element-by-element parity on grids that span several workgroups and end
+# in a ragged tail (count % 256 != 0)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,n,steps", [
+    (1, 1030, 40), (1, 2, 5), (1, 4, 7),
+    (2, 70, 30), (2, 2, 3), (2, 6, 9),
+    (3, 26, 12), (3, 2, 3), (3, 4, 5),
+])
+def test_parity_random_fields_fp64(dim, n, steps):
+    p = workloads.random_problem(dim, n, seed=1000 + dim * 100 + n, tau=0.02, amp=0.5)
+    assert_parity(p, steps, FP64_TOL)
+
+
+@pytest.mark.parametrize("dim,n,steps", [(1, 1030, 40), (2, 70, 30), (3, 26, 12)])
+def test_parity_random_fields_fp32(dim, n, steps):
+    p = workloads.random_problem(dim, n, seed=2000 + dim, tau=0.02, amp=0.5,
+                                 precision=workloads.FP32)
+    # the float32 state starts from rounded inputs: compare with the oracle
+    # started from the same rounded inputs
+    p.psi = p.psi.astype(np.complex64).astype(np.complex128)
+    p.u = p.u.astype(np.float32).astype(np.float64)
+    p.v = p.v.astype(np.float32).astype(np.float64)
+    assert_parity(p, steps, FP32_TOL)
+
+
+def test_parity_negative_kappa1_and_negative_tau():
+    p = workloads.random_problem(2, 34, seed=7, tau=-0.03, amp=0.5,
+                                 params=(-0.4, 0.1, 0.1, 0.2))
+    assert_parity(p, 20, FP64_TOL)
+
+
+def test_parity_1d_config_full_run():
+    p = workloads.config_1d()
+    got, ref = assert_parity(p, p.steps, FP64_TOL)
+
+
+@pytest.mark.parametrize("n,steps", [(128, 1000)])
+def test_parity_2d_config_recipe_reduced_grid(n, steps):
+    p = workloads.config_2d(n=n, steps=steps)
+    assert_parity(p, steps, FP64_TOL)
+
+
+def test_parity_3d_config_recipe_reduced_grid():
+    p = workloads.config_3d(n=32, steps=200)
+    assert_parity(p, p.steps, FP64_TOL)
+
+
+def test_parity_3d_config_recipe_reduced_grid_fp32():
+    p = workloads.config_3d(n=32, steps=200, precision=workloads.FP32)
+    assert_parity(p, p.steps, FP32_TOL)
+
+
+# ---------------------------------------------------------------------------
+# full-size configurations, a few steps (the oracle takes seconds per step)
+# ---------------------------------------------------------------------------
+def test_parity_2d_config_full_size_few_steps():
+    p = workloads.config_2d()
+    assert_parity(p, 4, FP64_TOL)
+
+
+def test_parity_3d_config_full_size_one_step():
+    p = workloads.config_3d()
+    assert_parity(p, 1, FP64_TOL)
+
+
+# ---------------------------------------------------------------------------
+# properties of the GPU path
+# ---------------------------------------------------------------------------
+def test_energy_matches_oracle_and_is_conserved():
+    p = workloads.config_3d(n=32, steps=200)
+    say("energy 3d n=32")
+    sim = kgs.simulation_from_problem(p)
+    e0 = sim.energy()
+    e0_ref = oracle.energy(grid_of(p), oracle.State.from_fields(p.psi, p.u, p.v))
+    assert abs(e0 - e0_ref) <= 1e-13 * abs(e0_ref)
+    sim.step(200)
+    e1 = sim.energy()
+    psi, u, v = sim.read_state()
+    sim.close()
+    e1_ref = oracle.energy(grid_of(p), oracle.State.from_fields(psi, u, v))
+    assert abs(e1 - e1_ref) <= 1e-13 * abs(e1_ref)
+    assert abs(e1 - e0) <= 1e-12 * abs(e0)
+
+
+def test_energy_conserved_1d_config_10k_steps():
+    p = workloads.config_1d()
+    say("energy drift 1d 1e4 steps")
+    sim = kgs.simulation_from_problem(p)
+    e0 = sim.energy()
+    worst = 0.0
+    for _ in range(10):
+        sim.step(1000)
+        worst = max(worst, abs(sim.energy() - e0) / abs(e0))
+    sim.close()
+    print("  relative drift", worst, flush=True)
+    assert worst <= 1e-12
+
+
+def test_energy_is_deterministic():
+    p = workloads.config_2d(n=256)
+    say("energy determinism 2d 256")
+    sim = kgs.simulation_from_problem(p)
+    sim.step(3)
+    es = {sim.energy() for _ in range(3)}
+    sim.close()
+    assert len(es) == 1
+
+
+@pytest.mark.parametrize("block", [64, 128, 512, 1024])
+def test_launch_shape_does_not_change_results(block):
+    p = workloads.random_problem(3, 18, seed=5, tau=0.05, amp=0.5)
+    say("block", block)
+    base = gpu_run(p, 6)
+    t = kgs.KgsTuning()
+    t.kernel = kgs.KGS_KERNEL_SWEEP
+    t.block = block
+    other = gpu_run(p, 6, tuning=t)
+    for a, b in zip(base, other):
+        assert np.array_equal(a, b)
+
+
+def test_steps_in_chunks_equal_steps_at_once_bitwise():
+    p = workloads.random_problem(2, 40, seed=9, tau=0.05, amp=0.5)
+    say("chunks")
+    a = gpu_run(p, 10)
+    b = gpu_run(p, 10, chunks=[3, 1, 6])
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_checkpoint_round_trip_bitwise():
+    p = workloads.random_problem(3, 16, seed=4, tau=0.05, amp=0.5)
+    say("checkpoint")
+    straight = gpu_run(p, 8)
+    sim = kgs.simulation_from_problem(p)
+    sim.step(4)
+    psi, u, v = sim.read_state()
+    sim.close()
+    sim = kgs.simulation_from_problem(p.with_(psi=psi, u=u, v=v))
+    sim.step(4)
+    resumed = sim.read_state()
+    sim.write_state(psi, u, v)
+    sim.step(4)
+    rewritten = sim.read_state()
+    sim.close()
+    for a, b, c in zip(straight, resumed, rewritten):
+        assert np.array_equal(a, b)
+        assert np.array_equal(a, c)
+
+
+def test_host_and_device_boundaries_agree():
+    p = workloads.random_problem(2, 22, seed=3, tau=0.05, amp=0.5)
+    say("host vs device")
+    a = gpu_run(p, 5, host=False)
+    b = gpu_run(p, 5, host=True)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_reversibility_on_gpu():
+    p = workloads.gaussian_problem(3, 24, 2, -5.0, 5.0, 0.05, 1)
+    say("reversibility")
+    sim = kgs.simulation_from_problem(p)
+    sim.step(10)
+    psi, u, v = sim.read_state()
+    sim.close()
+    back = kgs.simulation_from_problem(p.with_(psi=psi, u=u, v=v, tau=-p.tau))
+    back.step(10)
+    psi0, u0, v0 = back.read_state()
+    back.close()
+    scale = max(np.max(np.abs(p.psi)), np.max(np.abs(p.u)))
+    assert np.max(np.abs(psi0 - p.psi)) <= 1e-13 * scale
+    assert np.max(np.abs(u0 - p.u)) <= 1e-13 * scale
+    assert np.max(np.abs(v0 - p.v)) <= 1e-13 * scale
+
+
+def test_zero_steps_is_identity_and_bad_steps_rejected():
+    p = workloads.random_problem(1, 10, seed=1)
+    say("zero steps")
+    sim = kgs.simulation_from_problem(p)
+    sim.step(0)
+    psi, u, v = sim.read_state()
+    assert np.array_equal(psi, p.psi) and np.array_equal(u, p.u) and np.array_equal(v, p.v)
+    with pytest.raises(kgs.KgsError):
+        sim.step(-1)
+    sim.close()
+
+
+def test_nonfinite_energy_reported():
+    p = workloads.random_problem(2, 8, seed=1)
+    p.u = p.u.copy()
+    p.u[3, 3] = np.nan
+    say("nan energy")
+    sim = kgs.simulation_from_problem(p)
+    e = __import__("ctypes").c_double()
+    rc = kgs.lib().kgs_energy(sim.handle, __import__("ctypes").byref(e))
+    sim.close()
+    assert rc == kgs.KGS_ENONFINITE and not np.isfinite(e.value)
