@@ -34,6 +34,10 @@ def parse():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--kernel", choices=["auto", "sweep", "stream"], default="auto")
+    ap.add_argument("--tile", type=str, default=None,
+                    help="stream kernel shape tile_x,tile_y,chunk,steps_per_launch")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also time a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2,
                     help="oracle steps on the full grid for the CPU baseline")
@@ -70,12 +74,19 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     sim = kgs.simulation_from_problem(p)
-    if args.kernel != "auto":
+    if args.kernel != "auto" or args.tile:
         t = sim.tuning
-        t.kernel = {"sweep": kgs.KGS_KERNEL_SWEEP, "stream": kgs.KGS_KERNEL_STREAM}[args.kernel]
+        if args.kernel != "auto":
+            t.kernel = {"sweep": kgs.KGS_KERNEL_SWEEP, "stream": kgs.KGS_KERNEL_STREAM}[args.kernel]
+        if args.tile:
+            t.tile_x, t.tile_y, t.chunk, t.steps_per_launch = (int(v) for v in args.tile.split(","))
         sim.tuning = t
     info = sim.info()
-    launches_per_step = 2  # two colour sweeps per DP-AVF2 step (plus one per run)
+    tun = sim.tuning
+    if info.kernel == kgs.KGS_KERNEL_STREAM:
+        launches_per_step = 1.0 / tun.steps_per_launch  # plus one closing sweep per run
+    else:
+        launches_per_step = 2  # two colour sweeps per DP-AVF2 step (plus one per run)
 
     sim.step(args.warmup)
     sim.sync()
@@ -96,7 +107,7 @@ def main():
 
     updates = p.points * args.steps
     value = updates / wall
-    nlaunch = launches_per_step * args.steps + 1
+    nlaunch = int(round(launches_per_step * args.steps)) + 1
     avg_launch_s = kernel_ms / 1e3 / nlaunch
     # algorithmic bytes of one launch: one colour sweep advances half of the
     # points by one full step
@@ -117,12 +128,29 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"kgs3d n={p.n}^3 box [-8,8)^3 tau={p.tau} "
                                f"{args.precision} state, {args.steps} DP-AVF2 steps",
-                   "points": p.points, "kernel": int(info.kernel), "parallelism": "1 GPU"},
+                   "points": p.points, "kernel": int(info.kernel),
+                   "tile": [tun.tile_x, tun.tile_y, tun.chunk, tun.steps_per_launch]
+                   if info.kernel == kgs.KGS_KERNEL_STREAM else None,
+                   "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "energy_rel_drift": abs(e1 - e0) / abs(e0),
         "kernel_ms": kernel_ms,
     }
+    if args.calibrate_copy:
+        a = torch.empty(args.calibrate_copy << 17, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record(stream)
+        for _ in range(10):
+            b.copy_(a)
+        s1.record(stream)
+        torch.cuda.synchronize()
+        out["copy_calibration"] = {"bytes_read": a.numel() * 8, "bytes_written": a.numel() * 8,
+                                   "ms": s0.elapsed_time(s1) / 10,
+                                   "GBs": 2 * a.numel() * 8 / (s0.elapsed_time(s1) / 10 / 1e3) / 1e9}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(workloads.config_3d(n=args.n), args.cpu_steps)
     print(json.dumps(out), flush=True)

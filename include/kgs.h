@@ -136,19 +136,24 @@ const char *kgs_status_string(int status);
 enum {
     KGS_KERNEL_AUTO = 0,   /* library's choice for the grid                    */
     KGS_KERNEL_SWEEP = 1,  /* one launch per colour sweep, one thread per point */
-    KGS_KERNEL_STREAM = 2, /* 3-D only: z-streaming kernel, two colour sweeps
-                              (one full step) per launch, ping-pong buffers    */
+    KGS_KERNEL_STREAM = 2, /* 3-D only: z-streaming kernel, 2 or 4 colour sweeps
+                              (1 or 2 full steps) per launch between two state
+                              buffers (the handle then holds twice the state) */
     KGS_KERNEL_RESIDENT = 3, /* 1-D only: whole grid in one workgroup's LDS and
                                 registers, all steps in one launch             */
 };
 
 typedef struct {
     int32_t kernel;        /* KGS_KERNEL_*                                    */
-    int32_t block;         /* threads per workgroup for KGS_KERNEL_SWEEP (64..1024,
+    int32_t block;         /* KGS_KERNEL_SWEEP: threads per workgroup (64..1024,
                               multiple of 64); 0 = default                      */
-    int32_t tile_x;        /* KGS_KERNEL_STREAM: tile width in compressed x    */
-    int32_t tile_y;        /* KGS_KERNEL_STREAM: tile height in y              */
-    int32_t reserved[4];
+    int32_t tile_x;        /* KGS_KERNEL_STREAM: output tile width in points of
+                              one colour along the last axis                   */
+    int32_t tile_y;        /* KGS_KERNEL_STREAM: output tile height (axis 1)    */
+    int32_t chunk;         /* KGS_KERNEL_STREAM: planes of axis 0 per workgroup */
+    int32_t steps_per_launch; /* KGS_KERNEL_STREAM: 1 or 2 DP-AVF2 steps (2 or 4
+                              colour sweeps) per launch                        */
+    int32_t reserved[2];   /* must be 0                                       */
 } kgs_tuning;
 
 /* Read / replace the launch configuration of a handle (KGS_EINVAL for a

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <string>
 
 #include <hip/hip_runtime_api.h>
@@ -168,6 +169,16 @@ int64_t bytes_for(const kgs_config &c)
     return state + partials;
 }
 
+kgs::StreamShape stream_shape(const kgs_sim *s)
+{
+    kgs::StreamShape sh;
+    sh.tile_x = s->tuning.tile_x;
+    sh.tile_y = s->tuning.tile_y;
+    sh.chunk = s->tuning.chunk;
+    sh.steps = s->tuning.steps_per_launch;
+    return sh;
+}
+
 int check_device(kgs_sim *s)
 {
     int dev = -1;
@@ -292,6 +303,10 @@ int kgs_init(const kgs_config *cfg, const double *psi_re, const double *psi_im, 
     std::memset(&s->tuning, 0, sizeof(s->tuning));
     s->tuning.kernel = KGS_KERNEL_SWEEP;
     s->tuning.block = 256;
+    s->tuning.tile_x = 16;
+    s->tuning.tile_y = 32;
+    s->tuning.chunk = 32;
+    s->tuning.steps_per_launch = 1;
 
     hipError_t e = hipGetDevice(&s->device);
     if (e != hipSuccess) {
@@ -344,6 +359,22 @@ int kgs_step(kgs_sim *s, int64_t nsteps)
         hipError_t e = kgs::launch_sweep(s->geo, prec, s->state, kind, s->coef, block, s->stream);
         return e == hipSuccess ? KGS_OK : hip_fail(s, e, "sweep kernel launch");
     };
+    if (s->tuning.kernel == KGS_KERNEL_STREAM) {
+        // launches of 1 or 2 full steps (R, B[, R, B]) from one buffer to the
+        // other; the adjoint red sweep that closes the last step runs in place
+        const kgs::StreamShape sh = stream_shape(s);
+        bool first = true;
+        for (int64_t left = nsteps; left > 0 && rc == KGS_OK;) {
+            const int st = (sh.steps == 2 && left >= 2) ? 2 : 1;
+            hipError_t e = kgs::launch_stream3d(s->geo, prec, sh, 2 * st, s->state, s->state2,
+                                                first, s->coef, s->stream);
+            if (e != hipSuccess) return hip_fail(s, e, "stream kernel launch");
+            std::swap(s->state, s->state2);
+            first = false;
+            left -= st;
+        }
+        return sweep(kgs::PASS_R_ADJ);
+    }
     rc = sweep(kgs::PASS_R_BASE);
     for (int64_t i = 1; i < nsteps && rc == KGS_OK; ++i) {
         rc = sweep(kgs::PASS_B_FULL);
@@ -447,12 +478,29 @@ int kgs_set_tuning(kgs_sim *s, const kgs_tuning *t)
 {
     if (!s || !t) return fail(s, KGS_EINVAL, "handle or tuning is NULL");
     kgs_tuning nt = *t;
+    if (nt.reserved[0] || nt.reserved[1]) return fail(s, KGS_EINVAL, "reserved must be 0");
     if (nt.kernel == KGS_KERNEL_AUTO) nt.kernel = KGS_KERNEL_SWEEP;
-    if (nt.kernel != KGS_KERNEL_SWEEP)
-        return fail(s, KGS_EINVAL, "kernel family not available for this grid");
     if (nt.block == 0) nt.block = 256;
     if (nt.block < 64 || nt.block > 1024 || nt.block % 64)
         return fail(s, KGS_EINVAL, "block must be a multiple of 64 in [64, 1024]");
+    if (nt.kernel == KGS_KERNEL_STREAM) {
+        if (s->cfg.dim != 3) return fail(s, KGS_EINVAL, "the streaming kernel is 3-D only");
+        kgs::StreamShape sh = {nt.tile_x, nt.tile_y, nt.chunk, nt.steps_per_launch};
+        if (!kgs::stream3d_shape_ok(s->geo, sh, static_cast<int>(elem_bytes(s->cfg.precision))))
+            return fail(s, KGS_EINVAL, "tile/chunk/steps do not fit the streaming kernel");
+        if (!s->state2) {
+            int rc = check_device(s);
+            if (rc != KGS_OK) return rc;
+            hipError_t e = hipMalloc(&s->state2, 8 * s->plane_bytes);
+            if (e != hipSuccess) {
+                s->state2 = nullptr;
+                return hip_fail(s, e, "hipMalloc (second state buffer)");
+            }
+            s->device_bytes += static_cast<int64_t>(8 * s->plane_bytes);
+        }
+    } else if (nt.kernel != KGS_KERNEL_SWEEP) {
+        return fail(s, KGS_EINVAL, "kernel family not available for this grid");
+    }
     s->tuning = nt;
     return KGS_OK;
 }

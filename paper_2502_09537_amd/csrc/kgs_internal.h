@@ -71,7 +71,17 @@ struct Geometry {
     int64_t stride;  // elements between planes (count rounded up)
 };
 
-// Kernel launchers (kgs_sweep.hip, kgs_energy.hip).  They check the launch
+// Shape of the 3-D z-streaming kernel: output tile of tile_y rows x tile_x
+// compressed positions, chunk planes per workgroup, 1 or 2 DP-AVF2 steps
+// (2 or 4 colour sweeps) per launch.
+struct StreamShape {
+    int tile_x;
+    int tile_y;
+    int chunk;
+    int steps;
+};
+
+// Kernel launchers (kgs_sweep.hip, kgs_energy.hip, kgs_stream3d.hip).  They check the launch
 // shape against the geometry on the host and return hipErrorInvalidValue
 // rather than launch a kernel whose indexing would not fit.
 hipError_t launch_scatter(const Geometry &g, int precision, void *state, const double *P,
@@ -80,6 +90,11 @@ hipError_t launch_gather(const Geometry &g, int precision, const void *state, do
                          double *Q, double *U, double *V, hipStream_t s);
 hipError_t launch_sweep(const Geometry &g, int precision, void *state, int kind, const Coef &k,
                         int block, hipStream_t s);
+// `stages` (2 or 4) colour sweeps from `in` to `out` (distinct buffers);
+// the first stage is R_BASE when `first`, else R_ADJ_BASE.
+bool stream3d_shape_ok(const Geometry &g, const StreamShape &sh, int elem_bytes);
+hipError_t launch_stream3d(const Geometry &g, int precision, const StreamShape &sh, int stages,
+                           const void *in, void *out, bool first, const Coef &k, hipStream_t s);
 // Writes the double-double sum of the energy density (without h^dim) to
 // out[0] + out[1] (device memory); `partials` holds 2*energy_partial_slots()
 // doubles.

@@ -1,5 +1,7 @@
 // Device-side point updates of the explicit DP-AVF scheme (sec. 4.1 of the
-// paper, eq. scheme1 and scheme1-adj), shared by every sweep kernel.
+// paper, eq. scheme1 and scheme1-adj), shared by every sweep kernel.  The
+// library is compiled with -ffp-contract=off and every fused multiply-add is
+// written out, so all kernels round identically and agree bitwise.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -16,12 +18,12 @@ namespace kgs {
 __device__ __forceinline__ void psi_update(const Coef &k, double &pr, double &pi, double u,
                                            double sr, double si)
 {
-    const double c = k.a - k.e * u;
-    const double nr = c * pr - pi - k.b * sr;
-    const double ni = pr + c * pi - k.b * si;
-    const double inv = 1.0 / (1.0 + c * c);
-    pr = (ni - c * nr) * inv;
-    pi = -(nr + c * ni) * inv;
+    const double c = fma(-k.e, u, k.a);                // a - e u
+    const double nr = fma(-k.b, sr, fma(c, pr, -pi));  // c pr - pi - b sr
+    const double ni = fma(-k.b, si, fma(c, pi, pr));   // pr + c pi - b si
+    const double inv = 1.0 / fma(c, c, 1.0);
+    pr = fma(-c, nr, ni) * inv;                        // (ni - c nr) / (1 + c^2)
+    pi = -fma(c, ni, nr) * inv;                        // -(nr + c ni) / (1 + c^2)
 }
 
 // (u, v) at one point, given the neighbour sum su of u and the value |psi|^2
@@ -34,11 +36,11 @@ __device__ __forceinline__ void psi_update(const Coef &k, double &pr, double &pi
 __device__ __forceinline__ void uv_update(const Coef &k, double pr, double pi, double &u,
                                           double &v, double su)
 {
-    const double A = pr * pr + pi * pi;
-    const double r1 = u + k.t2 * v;
-    const double r2 = v - k.beta * u + k.s * su + k.g * A;
-    const double xu = r1 + k.t2 * r2;
-    const double xv = r2 - k.beta * r1;
+    const double A = fma(pr, pr, pi * pi);
+    const double r1 = fma(k.t2, v, u);
+    const double r2 = fma(k.g, A, fma(k.s, su, fma(-k.beta, u, v)));
+    const double xu = fma(k.t2, r2, r1);
+    const double xv = fma(-k.beta, r1, r2);
     u = fma(xu, k.rd_hi, xu * k.rd_lo);
     v = fma(xv, k.rd_hi, xv * k.rd_lo);
 }

@@ -45,7 +45,8 @@ class KgsTuning(ctypes.Structure):
     _fields_ = [
         ("kernel", ctypes.c_int32), ("block", ctypes.c_int32),
         ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("chunk", ctypes.c_int32), ("steps_per_launch", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 

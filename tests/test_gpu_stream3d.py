@@ -1,0 +1,87 @@
+"""GPU: the 3-D z-streaming kernel (1 or 2 DP-AVF2 steps per launch, ping-pong
+buffers) gives bitwise the same state as the one-sweep-per-launch kernel, for
+every tile/chunk shape, and matches the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_09537_amd import kgs, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def tuning(tile_x, tile_y, chunk, spl):
+    t = kgs.KgsTuning()
+    t.kernel = kgs.KGS_KERNEL_STREAM
+    t.block = 256
+    t.tile_x, t.tile_y, t.chunk, t.steps_per_launch = tile_x, tile_y, chunk, spl
+    return t
+
+
+def run(p, steps, t=None):
+    sim = kgs.simulation_from_problem(p, tuning=t)
+    try:
+        sim.step(steps)
+        e = sim.energy()
+        return sim.read_state(), e
+    finally:
+        sim.close()
+
+
+SHAPES = [
+    # n, steps, tile_x, tile_y, chunk, steps per launch
+    (26, 5, 8, 6, 5, 1),
+    (26, 5, 8, 6, 5, 2),
+    (32, 4, 16, 32, 32, 1),
+    (32, 3, 16, 17, 32, 2),
+    (6, 3, 16, 16, 16, 1),
+    (6, 3, 2, 3, 2, 2),
+    (2, 2, 1, 1, 1, 2),
+    (40, 2, 20, 12, 7, 1),
+]
+
+
+@pytest.mark.parametrize("prec", [workloads.FP64, workloads.FP32])
+@pytest.mark.parametrize("n,steps,tx,ty,chunk,spl", SHAPES)
+def test_stream_equals_sweep_bitwise(n, steps, tx, ty, chunk, spl, prec):
+    p = workloads.random_problem(3, n, seed=31 + n, tau=0.04, amp=0.5, precision=prec)
+    say("stream vs sweep", n, steps, tx, ty, chunk, spl, prec)
+    (a, ea) = run(p, steps)
+    (b, eb) = run(p, steps, tuning(tx, ty, chunk, spl))
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    assert ea == eb
+
+
+def test_stream_matches_oracle_3d_config_reduced():
+    p = workloads.config_3d(n=32, steps=200)
+    say("stream vs oracle 32^3 x 200")
+    (psi, u, v), e = run(p, p.steps, tuning(16, 17, 32, 2))
+    s = oracle.State.from_fields(p.psi, p.u, p.v)
+    g = oracle.Grid(3, p.n, p.lo, p.hi, p.kappa1, p.kappa2, p.mu, p.gamma)
+    oracle.step(g, p.tau, s, p.steps)
+    assert np.max(np.abs(psi - s.psi)) <= 1e-12 * np.max(np.abs(s.psi))
+    assert np.max(np.abs(u - s.U)) <= 1e-12 * np.max(np.abs(s.U))
+    assert np.max(np.abs(v - s.V)) <= 1e-12 * np.max(np.abs(s.U))
+
+
+def test_stream_rejects_bad_shapes():
+    p = workloads.random_problem(3, 8, seed=1)
+    say("bad shapes")
+    sim = kgs.simulation_from_problem(p)
+    for bad in (tuning(0, 4, 4, 1), tuning(4, 4, 4, 3), tuning(64, 64, 4, 1), tuning(4, 4, 0, 1)):
+        with pytest.raises(kgs.KgsError):
+            sim.tuning = bad
+    sim.close()
+    p2 = workloads.random_problem(2, 8, seed=1)
+    sim = kgs.simulation_from_problem(p2)
+    with pytest.raises(kgs.KgsError):
+        sim.tuning = tuning(4, 4, 4, 1)
+    sim.close()
