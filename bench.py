@@ -22,6 +22,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_3d256.json")
+KERNEL_SOURCES = ("kgs_stream3d.hip", "kgs_sweep.hip", "kgs_point.h", "kgs_internal.h")
 ALGO_BYTES = {"fp64": 64, "fp32": 32}  # read + write (P, Q, U, V) once per point-step
 METRIC = "lattice-point updates/s + % HBM roofline (3D 256³ FP64); served p50/p99"
 
@@ -42,6 +44,32 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=2,
                     help="oracle steps on the full grid for the CPU baseline")
     return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2502_09537_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(key: str):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs (each scaled by what the counter reads for a
+    plain copy of known size), or None if the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = data.get(key)
+    if not e or e.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return (e["fetch_kib_per_launch"] * e["fetch_scale"] +
+            e["write_kib_per_launch"] * e["write_scale"]) * 1024.0
 
 
 def cpu_baseline(problem, steps):
@@ -83,11 +111,6 @@ def main():
         sim.tuning = t
     info = sim.info()
     tun = sim.tuning
-    if info.kernel == kgs.KGS_KERNEL_STREAM:
-        launches_per_step = 1.0 / tun.steps_per_launch  # plus one closing sweep per run
-    else:
-        launches_per_step = 2  # two colour sweeps per DP-AVF2 step (plus one per run)
-
     sim.step(args.warmup)
     sim.sync()
     e0 = sim.energy()
@@ -103,16 +126,35 @@ def main():
     t1 = time.perf_counter()
     wall = t1 - t0
     kernel_ms = start.elapsed_time(stop)
+
+    # the dominant kernel's own average duration: a kgs_step call of K steps
+    # is K/spl streaming launches (or 2K sweeps) plus one closing sweep, so
+    # time 2- and 4-step calls and take the difference
+    def timed(k):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        sim.step(k)
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+    spl = tun.steps_per_launch if info.kernel == kgs.KGS_KERNEL_STREAM else 1
+    per = 1 if info.kernel == kgs.KGS_KERNEL_STREAM else 2  # launches per spl steps
+    t_small = min(timed(2 * spl) for _ in range(3))
+    t_big = min(timed(4 * spl) for _ in range(3))
+    unit_ms = (t_big - t_small) / (2 * per)           # one dominant-kernel launch
+    closing_ms = max(t_small - 2 * per * unit_ms, 0.0)  # the closing sweep
     sim.close()
 
     updates = p.points * args.steps
     value = updates / wall
-    nlaunch = int(round(launches_per_step * args.steps)) + 1
-    avg_launch_s = kernel_ms / 1e3 / nlaunch
-    # algorithmic bytes of one launch: one colour sweep advances half of the
-    # points by one full step
-    algo_per_launch = ALGO_BYTES[args.precision] * p.points * args.steps / nlaunch
+    n_dom = int(round(args.steps / spl * per))
+    avg_launch_s = max(kernel_ms - closing_ms, 1e-9) / 1e3 / n_dom
+    # algorithmic bytes of one launch: a streaming launch advances every point
+    # by spl steps; a sweep advances half of the points by one step
+    algo_per_launch = ALGO_BYTES[args.precision] * p.points * (spl if per == 1 else 0.5)
     achieved = algo_per_launch / avg_launch_s / 1e9
+    key = f"{args.precision}:" + ("stream%d" % spl if per == 1 else "sweep")
+    traffic = measured_traffic(key) if args.n == 256 else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -133,7 +175,9 @@ def main():
                    if info.kernel == kgs.KGS_KERNEL_STREAM else None,
                    "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": key, "avg_launch_us": avg_launch_s * 1e6,
+                     "algorithmic_bytes_per_launch": algo_per_launch},
         "energy_rel_drift": abs(e1 - e0) / abs(e0),
         "kernel_ms": kernel_ms,
     }

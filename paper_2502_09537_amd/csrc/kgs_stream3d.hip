@@ -100,49 +100,59 @@ stream3d_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t stride, i
     const int i_yp = min(lty + 1, BY - 1) * BX + ltx;
 
     const int64_t plane_elems = static_cast<int64_t>(n) * H;
-    const T *in_c[2] = {in, in + 4 * stride};
-    T *out_c[2] = {out, out + 4 * stride};
+    const int64_t col = static_cast<int64_t>(y) * H + xh;  // offset inside a plane
+    T *const out_c[2] = {out, out + 4 * stride};
 
     // FIFOs (slot 0 = produced at this step): level 0 red (2 slots), level 0
     // blue (3 slots), levels 1..S-1 (3 slots, colour of the producing stage)
     Vals<T> r0[2], b0[3], f[S - 1][3];
-    Vals<T> next_r, next_b;  // prefetched input plane
+    Vals<T> pre_r[2], pre_b[2];  // input planes prefetched two steps ahead
     {
         const Vals<T> zero = {{T(0), T(0), T(0), T(0)}};
-        r0[0] = r0[1] = b0[0] = b0[1] = b0[2] = next_r = next_b = zero;
+        r0[0] = r0[1] = b0[0] = b0[1] = b0[2] = zero;
+        pre_r[0] = pre_r[1] = pre_b[0] = pre_b[1] = zero;
 #pragma unroll
         for (int j = 0; j < S - 1; ++j) f[j][0] = f[j][1] = f[j][2] = zero;
     }
 
-    auto load_plane = [&](int p, Vals<T> &rv, Vals<T> &bv) {
-        const int z = wrap(z0 - S + p, n);
-        const int64_t e = static_cast<int64_t>(z) * plane_elems + static_cast<int64_t>(y) * H + xh;
+    auto load_plane = [&](int z, Vals<T> &rv, Vals<T> &bv) {
+        const T *pr_ = in + static_cast<int64_t>(z) * plane_elems + col;
+        const T *pb_ = pr_ + 4 * stride;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            rv.f[q] = in_c[RED][q * stride + e];
-            bv.f[q] = in_c[BLUE][q * stride + e];
+            rv.f[q] = pr_[q * stride];
+            bv.f[q] = pb_[q * stride];
         }
     };
 
     const int steps = L + 2 * S;
-    if (live) load_plane(0, next_r, next_b);
+    // planes are tracked wrapped and advanced by one per step
+    int z_load = wrap(z0 - S, n);  // plane loaded (consumed) at step p
+    int z_pf = z_load;             // next plane to prefetch
+    if (live) load_plane(z_pf, pre_r[0], pre_b[0]);
+    z_pf = z_pf + 1 == n ? 0 : z_pf + 1;
+    if (live && steps > 1) load_plane(z_pf, pre_r[1], pre_b[1]);
+    z_pf = z_pf + 1 == n ? 0 : z_pf + 1;
 
     for (int p = 0; p < steps; ++p) {
         const int rb = (p - 1) & 1, wb = p & 1;
-        // shift the level-0 FIFO and take the prefetched plane
+        // shift the level-0 FIFO and take the plane prefetched two steps ago
         r0[1] = r0[0];
         b0[2] = b0[1];
         b0[1] = b0[0];
-        r0[0] = next_r;
-        b0[0] = next_b;
-        if (live && p + 1 < steps) load_plane(p + 1, next_r, next_b);
+        r0[0] = pre_r[0];
+        b0[0] = pre_b[0];
+        pre_r[0] = pre_r[1];
+        pre_b[0] = pre_b[1];
+        if (live && p + 2 < steps) load_plane(z_pf, pre_r[1], pre_b[1]);
+        z_pf = z_pf + 1 == n ? 0 : z_pf + 1;
 
-        const int lp = z0 - S + p;  // unwrapped plane loaded at this step
 #pragma unroll
         for (int j = 0; j < S; ++j) {
             if (p < 2 * j + 2) continue;  // pipeline not yet filled for stage j
             const int c = j & 1;
-            const int z = wrap(lp - 1 - j, n);
+            int z = z_load - 1 - j;  // plane updated by stage j (wrapped)
+            while (z < 0) z += n;
             const int o = (z + y + c) & 1;  // x-offset of colour c in this row
             const int i_xm = lty * BX + max(ltx - 1 + o, 0);
             const int i_xp = lty * BX + min(ltx + o, BX - 1);
@@ -184,17 +194,18 @@ stream3d_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t stride, i
                 f[j][0] = res;
             } else if (in_tile) {
                 // final level S at plane z: colour c from this stage, the
-                // other colour from stage S-2 one step ago (or level 0)
+                // other colour from stage S-2 one step ago
                 const Vals<T> &oth = f[S - 2][1];
-                const int64_t e =
-                    static_cast<int64_t>(z) * plane_elems + static_cast<int64_t>(y) * H + xh;
+                T *oc = out_c[c] + static_cast<int64_t>(z) * plane_elems + col;
+                T *oo = out_c[c ^ 1] + static_cast<int64_t>(z) * plane_elems + col;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    out_c[c][q * stride + e] = res.f[q];
-                    out_c[c ^ 1][q * stride + e] = oth.f[q];
+                    oc[q * stride] = res.f[q];
+                    oo[q * stride] = oth.f[q];
                 }
             }
         }
+        z_load = z_load + 1 == n ? 0 : z_load + 1;
         // publish the newest plane of every level that a stage reads next step
         if (live) {
             T *pw = lds + static_cast<size_t>(wb) * S * 3 * NT;

@@ -76,6 +76,8 @@ template <int DIM, typename T, int KIND>
 __global__ void __launch_bounds__(1024)
 sweep_kernel(T *__restrict__ base, int64_t stride, int n, int colour, Coef k, int64_t count)
 {
+    // (Giving each XCD a contiguous eighth of the rows measured 3% slower
+    // than the hardware's round-robin order on 256^3, so blocks stay in order.)
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= count) return;
     const int H = n >> 1;

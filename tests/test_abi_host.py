@@ -101,8 +101,12 @@ def test_null_arguments(L):
 
 
 def test_required_bytes(L):
+    # 3-D float64 grids run the ping-pong streaming kernel by default: two states
     cfg = good(dim=3, n=256)
     state = 8 * (256 ** 3 // 2) * 8
-    assert state <= kgs.required_bytes(cfg) < state + (1 << 20)
+    assert 2 * state <= kgs.required_bytes(cfg) < 2 * state + (1 << 20)
     cfg32 = good(dim=3, n=256, precision=kgs.KGS_FP32)
-    assert kgs.required_bytes(cfg32) < kgs.required_bytes(cfg)
+    assert state // 2 <= kgs.required_bytes(cfg32) < state // 2 + (1 << 20)
+    cfg2 = good(dim=2, n=1024)
+    state2 = 8 * (1024 ** 2 // 2) * 8
+    assert state2 <= kgs.required_bytes(cfg2) < state2 + (1 << 20)

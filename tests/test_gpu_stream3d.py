@@ -25,8 +25,15 @@ def tuning(tile_x, tile_y, chunk, spl):
     return t
 
 
+def sweep_tuning():
+    t = kgs.KgsTuning()
+    t.kernel = kgs.KGS_KERNEL_SWEEP
+    t.block = 256
+    return t
+
+
 def run(p, steps, t=None):
-    sim = kgs.simulation_from_problem(p, tuning=t)
+    sim = kgs.simulation_from_problem(p, tuning=t if t is not None else sweep_tuning())
     try:
         sim.step(steps)
         e = sim.energy()
@@ -85,3 +92,16 @@ def test_stream_rejects_bad_shapes():
     with pytest.raises(kgs.KgsError):
         sim.tuning = tuning(4, 4, 4, 1)
     sim.close()
+
+
+def test_default_3d_fp64_uses_streaming_kernel_and_matches_sweep_at_full_size():
+    p = workloads.config_3d(n=256)
+    say("full-size default (streaming) vs sweep, 2 steps")
+    sim = kgs.simulation_from_problem(p)
+    assert sim.tuning.kernel == kgs.KGS_KERNEL_STREAM
+    sim.step(2)
+    a = sim.read_state()
+    sim.close()
+    (b, _) = run(p, 2)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
