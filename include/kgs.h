@@ -176,6 +176,40 @@ int kgs_get_info(const kgs_sim *sim, kgs_info *out);
  * invalid cfg); lets a caller admit simulations against a memory budget. */
 int64_t kgs_required_bytes(const kgs_config *cfg);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent simulations (any dimensions, sizes, parameters
+ * and precisions) advanced together.  Each colour sweep is one launch per
+ * (dimension, precision) class over all members instead of one launch per
+ * simulation; a uniform run can be captured once in a hipGraph and replayed.
+ * Every member ends bitwise where kgs_step would have left it (points of one
+ * colour are independent, sec. 4.2, so the launch layout does not matter).
+ * ---------------------------------------------------------------------- */
+typedef struct kgs_batch kgs_batch;
+
+/* Group `count` distinct simulations (same GPU) into a batch whose work is
+ * ordered on `stream` (hipStream_t or NULL): it starts after earlier work on
+ * `stream` and later work on `stream` waits for it.  The batch keeps
+ * pointers to the handles (not their data); free the batch before them.
+ * Members keep working on their own: the batch uses their current state. */
+int kgs_batch_create(kgs_sim *const *sims, int32_t count, void *stream, kgs_batch **out);
+
+/* Advance every member by nsteps DP-AVF2 steps (asynchronous). */
+int kgs_batch_step(kgs_batch *b, int64_t nsteps);
+
+/* Advance member i by nsteps[i] steps (uneven counts, 0 allowed) in one
+ * batched run: members that finish early drop out of the later launches. */
+int kgs_batch_step_each(kgs_batch *b, const int64_t *nsteps);
+
+/* With enable != 0, kgs_batch_step captures the launch sequence of a K-step
+ * run in a hipGraph the first time K is used and replays it afterwards. */
+int kgs_batch_set_graph(kgs_batch *b, int32_t enable);
+
+/* Wait for the batch's work and release it (not the member simulations). */
+int kgs_batch_free(kgs_batch *b);
+
+/* Message of the last failure of b (or of kgs_batch_create for NULL). */
+const char *kgs_batch_last_error(const kgs_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,25 +16,9 @@
 #include <hip/hip_runtime_api.h>
 
 #include "kgs_internal.h"
+#include "kgs_sim.h"
 
-struct kgs_sim {
-    kgs_config cfg;
-    kgs::Geometry geo;
-    double h;
-    double hd;             // h^dim
-    kgs::Coef coef;        // constants of one half step (tau/2)
-    kgs::EnergyCoef ecoef;
-    void *state = nullptr; // 8 colour-split planes
-    void *state2 = nullptr; // second copy for ping-pong kernels (3-D streaming)
-    size_t plane_bytes = 0;
-    double *partials = nullptr;  // energy partials, then the 2-double result
-    double *host_out = nullptr;  // pinned, 2 doubles
-    hipStream_t stream = nullptr;
-    int device = 0;
-    kgs_tuning tuning;
-    int64_t device_bytes = 0;
-    std::string err;
-};
+
 
 namespace {
 

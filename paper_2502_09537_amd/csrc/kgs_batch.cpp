@@ -1,0 +1,390 @@
+// Batches of simulations: many independent DP-AVF2 runs of uneven sizes
+// advanced together, one batched launch per colour sweep and per
+// (dimension, storage precision) class instead of one launch per simulation,
+// optionally with the whole step loop captured in a hipGraph and replayed.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime_api.h>
+
+#include "kgs.h"
+#include "kgs_internal.h"
+#include "kgs_sim.h"
+
+namespace {
+
+struct BatchClass {
+    int dim = 0, precision = 0;
+    std::vector<int> members;  // indices into kgs_batch::sims
+    kgs::BatchMember *d_members = nullptr;
+    kgs::BatchMember *h_members = nullptr;  // pinned staging
+    int64_t blocks = 0;
+};
+
+}  // namespace
+
+struct kgs_batch {
+    std::vector<kgs_sim *> sims;
+    std::vector<BatchClass> classes;
+    hipStream_t user = nullptr;  // caller's stream
+    hipStream_t own = nullptr;   // the batch's stream (capturable)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    int device = 0;
+    bool use_graph = false;
+    bool uploaded = false;  // descriptors copied to the device at least once
+    std::map<int64_t, hipGraphExec_t> graphs;  // uniform K-step runs
+    int *d_kinds = nullptr, *h_kinds = nullptr;  // per-launch member kinds
+    int64_t kinds_cap = 0;
+    std::string err;
+};
+
+namespace {
+
+int bfail(kgs_batch *b, int code, const std::string &msg)
+{
+    if (b) b->err = msg;
+    return code;
+}
+
+int bhip(kgs_batch *b, hipError_t e, const char *what)
+{
+    return bfail(b, e == hipErrorOutOfMemory ? KGS_ENOMEM : KGS_EDEVICE,
+                 std::string(what) + ": " + hipGetErrorName(e));
+}
+
+thread_local std::string g_batch_err;
+
+void destroy(kgs_batch *b)
+{
+    for (auto &kv : b->graphs)
+        if (hipGraphExecDestroy(kv.second) != hipSuccess) {
+        }
+    b->graphs.clear();
+    for (auto &c : b->classes) {
+        if (c.d_members && hipFree(c.d_members) != hipSuccess) {
+        }
+        if (c.h_members && hipHostFree(c.h_members) != hipSuccess) {
+        }
+    }
+    if (b->d_kinds && hipFree(b->d_kinds) != hipSuccess) {
+    }
+    if (b->h_kinds && hipHostFree(b->h_kinds) != hipSuccess) {
+    }
+    if (b->ev_in && hipEventDestroy(b->ev_in) != hipSuccess) {
+    }
+    if (b->ev_out && hipEventDestroy(b->ev_out) != hipSuccess) {
+    }
+    if (b->own && hipStreamDestroy(b->own) != hipSuccess) {
+    }
+}
+
+// Copy every member's current state buffer (the 3-D streaming kernel swaps
+// buffers) into the device descriptors when one has changed.  The pinned
+// staging may still be read by an earlier queued copy, so wait for the batch
+// stream before rewriting it.
+int refresh_descriptors(kgs_batch *b)
+{
+    bool changed = false;
+    for (auto &c : b->classes)
+        for (size_t i = 0; i < c.members.size(); ++i)
+            changed |= c.h_members[i].state != b->sims[c.members[i]]->state;
+    if (!changed && b->uploaded) return KGS_OK;
+    hipError_t e = hipStreamSynchronize(b->own);
+    if (e != hipSuccess) return bhip(b, e, "hipStreamSynchronize");
+    for (auto &c : b->classes) {
+        for (size_t i = 0; i < c.members.size(); ++i) c.h_members[i].state = b->sims[c.members[i]]->state;
+        e = hipMemcpyAsync(c.d_members, c.h_members, c.members.size() * sizeof(kgs::BatchMember),
+                           hipMemcpyHostToDevice, b->own);
+        if (e != hipSuccess) return bhip(b, e, "hipMemcpyAsync (batch descriptors)");
+    }
+    b->uploaded = true;
+    return KGS_OK;
+}
+
+// Launch sequence of a uniform K-step run: R_BASE, (B_FULL, R_ADJ_BASE)^(K-1),
+// B_FULL, R_ADJ, each as one batched launch per class.
+hipError_t enqueue_uniform(kgs_batch *b, int64_t nsteps)
+{
+    auto sweep = [&](int kind) {
+        for (auto &c : b->classes) {
+            hipError_t e = kgs::launch_batch_sweep(c.dim, c.precision, c.d_members,
+                                                   static_cast<int>(c.members.size()), c.blocks,
+                                                   nullptr, 0, kind, b->own);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    hipError_t e = sweep(kgs::PASS_R_BASE);
+    for (int64_t i = 1; i < nsteps && e == hipSuccess; ++i) {
+        e = sweep(kgs::PASS_B_FULL);
+        if (e == hipSuccess) e = sweep(kgs::PASS_R_ADJ_BASE);
+    }
+    if (e == hipSuccess) e = sweep(kgs::PASS_B_FULL);
+    if (e == hipSuccess) e = sweep(kgs::PASS_R_ADJ);
+    return e;
+}
+
+int begin(kgs_batch *b)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return bhip(b, e, "hipGetDevice");
+    if (dev != b->device && (e = hipSetDevice(b->device)) != hipSuccess)
+        return bhip(b, e, "hipSetDevice");
+    if ((e = hipEventRecord(b->ev_in, b->user)) != hipSuccess) return bhip(b, e, "hipEventRecord");
+    if ((e = hipStreamWaitEvent(b->own, b->ev_in, 0)) != hipSuccess)
+        return bhip(b, e, "hipStreamWaitEvent");
+    return refresh_descriptors(b);
+}
+
+int end(kgs_batch *b)
+{
+    hipError_t e = hipEventRecord(b->ev_out, b->own);
+    if (e != hipSuccess) return bhip(b, e, "hipEventRecord");
+    if ((e = hipStreamWaitEvent(b->user, b->ev_out, 0)) != hipSuccess)
+        return bhip(b, e, "hipStreamWaitEvent");
+    return KGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *kgs_batch_last_error(const kgs_batch *b) { return b ? b->err.c_str() : g_batch_err.c_str(); }
+
+int kgs_batch_create(kgs_sim *const *sims, int32_t count, void *stream, kgs_batch **out)
+{
+    if (!out) {
+        g_batch_err = "out is NULL";
+        return KGS_EINVAL;
+    }
+    *out = nullptr;
+    if (!sims || count < 1) {
+        g_batch_err = "need at least one simulation";
+        return KGS_EINVAL;
+    }
+    kgs_batch *b = new (std::nothrow) kgs_batch();
+    if (!b) {
+        g_batch_err = "host allocation failed";
+        return KGS_ENOMEM;
+    }
+    b->user = static_cast<hipStream_t>(stream);
+    int code = KGS_OK;
+    for (int32_t i = 0; i < count && code == KGS_OK; ++i) {
+        if (!sims[i]) code = bfail(b, KGS_EINVAL, "simulation pointer is NULL");
+        else if (i > 0 && sims[i]->device != sims[0]->device)
+            code = bfail(b, KGS_EINVAL, "all simulations must live on one GPU");
+        else if (std::find(b->sims.begin(), b->sims.end(), sims[i]) != b->sims.end())
+            code = bfail(b, KGS_EINVAL, "a simulation appears twice");
+        else b->sims.push_back(sims[i]);
+    }
+    hipError_t e = hipSuccess;
+    if (code == KGS_OK) {
+        b->device = sims[0]->device;
+        if ((e = hipSetDevice(b->device)) != hipSuccess) code = bhip(b, e, "hipSetDevice");
+    }
+    if (code == KGS_OK && (e = hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking)) != hipSuccess)
+        code = bhip(b, e, "hipStreamCreate");
+    if (code == KGS_OK && (e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming)) != hipSuccess)
+        code = bhip(b, e, "hipEventCreate");
+    if (code == KGS_OK && (e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming)) != hipSuccess)
+        code = bhip(b, e, "hipEventCreate");
+    // group by (dim, precision), larger simulations first
+    if (code == KGS_OK) {
+        std::vector<int> order(b->sims.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = static_cast<int>(i);
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+            return b->sims[x]->geo.count > b->sims[y]->geo.count;
+        });
+        for (int i : order) {
+            const kgs_sim *s = b->sims[i];
+            auto it = std::find_if(b->classes.begin(), b->classes.end(), [&](const BatchClass &c) {
+                return c.dim == s->cfg.dim && c.precision == s->cfg.precision;
+            });
+            if (it == b->classes.end()) {
+                b->classes.emplace_back();
+                it = b->classes.end() - 1;
+                it->dim = s->cfg.dim;
+                it->precision = s->cfg.precision;
+            }
+            it->members.push_back(i);
+        }
+        const int bb = kgs::batch_block();
+        for (auto &c : b->classes) {
+            const size_t bytes = c.members.size() * sizeof(kgs::BatchMember);
+            if ((e = hipMalloc(reinterpret_cast<void **>(&c.d_members), bytes)) != hipSuccess) {
+                code = bhip(b, e, "hipMalloc (batch descriptors)");
+                break;
+            }
+            if ((e = hipHostMalloc(reinterpret_cast<void **>(&c.h_members), bytes,
+                                   hipHostMallocDefault)) != hipSuccess) {
+                code = bhip(b, e, "hipHostMalloc (batch descriptors)");
+                break;
+            }
+            int64_t blocks = 0;
+            for (size_t i = 0; i < c.members.size(); ++i) {
+                const kgs_sim *s = b->sims[c.members[i]];
+                kgs::BatchMember &m = c.h_members[i];
+                std::memset(&m, 0, sizeof(m));
+                m.state = s->state;
+                m.stride = s->geo.stride;
+                m.count = s->geo.count;
+                m.block_begin = blocks;
+                m.k = s->coef;
+                m.n = s->geo.n;
+                blocks += (s->geo.count + bb - 1) / bb;
+            }
+            if (blocks > 0x7fffffff) {
+                code = bfail(b, KGS_EINVAL, "batch too large for one launch");
+                break;
+            }
+            c.blocks = blocks;
+        }
+    }
+    if (code != KGS_OK) {
+        g_batch_err = b->err;
+        destroy(b);
+        delete b;
+        return code;
+    }
+    *out = b;
+    return KGS_OK;
+}
+
+int kgs_batch_set_graph(kgs_batch *b, int32_t enable)
+{
+    if (!b) return KGS_EINVAL;
+    b->use_graph = enable != 0;
+    return KGS_OK;
+}
+
+int kgs_batch_step(kgs_batch *b, int64_t nsteps)
+{
+    if (!b) return KGS_EINVAL;
+    if (nsteps < 0) return bfail(b, KGS_EINVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return KGS_OK;
+    int rc = begin(b);
+    if (rc != KGS_OK) return rc;
+    hipError_t e;
+    if (b->use_graph) {
+        auto it = b->graphs.find(nsteps);
+        if (it == b->graphs.end()) {
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ge = nullptr;
+            if ((e = hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                return bhip(b, e, "hipStreamBeginCapture");
+            hipError_t le = enqueue_uniform(b, nsteps);
+            e = hipStreamEndCapture(b->own, &g);
+            if (le != hipSuccess) {
+                if (g && hipGraphDestroy(g) != hipSuccess) {
+                }
+                return bhip(b, le, "batched sweep launch (capture)");
+            }
+            if (e != hipSuccess) return bhip(b, e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            if (hipGraphDestroy(g) != hipSuccess) {
+            }
+            if (e != hipSuccess) return bhip(b, e, "hipGraphInstantiate");
+            it = b->graphs.emplace(nsteps, ge).first;
+        }
+        if ((e = hipGraphLaunch(it->second, b->own)) != hipSuccess) return bhip(b, e, "hipGraphLaunch");
+    } else {
+        if ((e = enqueue_uniform(b, nsteps)) != hipSuccess)
+            return bhip(b, e, "batched sweep launch");
+    }
+    return end(b);
+}
+
+int kgs_batch_step_each(kgs_batch *b, const int64_t *nsteps)
+{
+    if (!b || !nsteps) return bfail(b, KGS_EINVAL, "batch or nsteps is NULL");
+    int64_t kmax = 0;
+    for (size_t i = 0; i < b->sims.size(); ++i) {
+        if (nsteps[i] < 0) return bfail(b, KGS_EINVAL, "nsteps must be >= 0");
+        kmax = std::max(kmax, nsteps[i]);
+    }
+    if (kmax == 0) return KGS_OK;
+    // launch sequence per class: red 0, blue 0, red 1, ..., blue kmax-1, red kmax
+    const int64_t launches = 2 * kmax + 1;
+    size_t nmax = 0;
+    for (auto &c : b->classes) nmax = std::max(nmax, c.members.size());
+    const int64_t need = launches * static_cast<int64_t>(nmax) * static_cast<int64_t>(b->classes.size());
+    if (need > (int64_t(1) << 31)) return bfail(b, KGS_EINVAL, "schedule too large");
+    int rc = begin(b);
+    if (rc != KGS_OK) return rc;
+    hipError_t e;
+    if (need > b->kinds_cap) {
+        // the previous table may still be read by queued work
+        if ((e = hipStreamSynchronize(b->own)) != hipSuccess) return bhip(b, e, "hipStreamSynchronize");
+        if (b->d_kinds && hipFree(b->d_kinds) != hipSuccess) {
+        }
+        if (b->h_kinds && hipHostFree(b->h_kinds) != hipSuccess) {
+        }
+        b->d_kinds = nullptr;
+        b->h_kinds = nullptr;
+        b->kinds_cap = 0;
+        if ((e = hipMalloc(reinterpret_cast<void **>(&b->d_kinds), need * sizeof(int))) != hipSuccess)
+            return bhip(b, e, "hipMalloc (schedule)");
+        if ((e = hipHostMalloc(reinterpret_cast<void **>(&b->h_kinds), need * sizeof(int),
+                               hipHostMallocDefault)) != hipSuccess)
+            return bhip(b, e, "hipHostMalloc (schedule)");
+        b->kinds_cap = need;
+    } else if ((e = hipStreamSynchronize(b->own)) != hipSuccess) {
+        // pinned staging is reused: wait until the previous schedule was consumed
+        return bhip(b, e, "hipStreamSynchronize");
+    }
+    // kinds table: [class][launch][member]
+    int64_t off = 0;
+    std::vector<int64_t> class_off;
+    for (auto &c : b->classes) {
+        class_off.push_back(off);
+        const int nm = static_cast<int>(c.members.size());
+        for (int64_t L = 0; L < launches; ++L) {
+            const int64_t i = L / 2;  // step index
+            const bool red = (L % 2) == 0;
+            for (int m = 0; m < nm; ++m) {
+                const int64_t k = nsteps[c.members[m]];
+                int kind = -1;
+                if (red) {
+                    if (k > 0 && i == 0) kind = kgs::PASS_R_BASE;
+                    else if (i > 0 && i < k) kind = kgs::PASS_R_ADJ_BASE;
+                    else if (k > 0 && i == k) kind = kgs::PASS_R_ADJ;
+                } else if (i < k) {
+                    kind = kgs::PASS_B_FULL;
+                }
+                b->h_kinds[off + L * nm + m] = kind;
+            }
+        }
+        off += launches * nm;
+    }
+    if ((e = hipMemcpyAsync(b->d_kinds, b->h_kinds, off * sizeof(int), hipMemcpyHostToDevice,
+                            b->own)) != hipSuccess)
+        return bhip(b, e, "hipMemcpyAsync (schedule)");
+    for (int64_t L = 0; L < launches; ++L) {
+        for (size_t ci = 0; ci < b->classes.size(); ++ci) {
+            auto &c = b->classes[ci];
+            e = kgs::launch_batch_sweep(c.dim, c.precision, c.d_members,
+                                        static_cast<int>(c.members.size()), c.blocks,
+                                        b->d_kinds + class_off[ci], static_cast<int>(L), -1, b->own);
+            if (e != hipSuccess) return bhip(b, e, "batched sweep launch");
+        }
+    }
+    return end(b);
+}
+
+int kgs_batch_free(kgs_batch *b)
+{
+    if (!b) return KGS_OK;
+    int rc = KGS_OK;
+    if (hipSetDevice(b->device) != hipSuccess || hipStreamSynchronize(b->own) != hipSuccess)
+        rc = KGS_EDEVICE;
+    destroy(b);
+    delete b;
+    return rc;
+}
+
+}  // extern "C"

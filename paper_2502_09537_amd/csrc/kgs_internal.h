@@ -81,6 +81,18 @@ struct StreamShape {
     int steps;
 };
 
+// One member of a batched sweep (kgs_batch.hip): a simulation's current
+// state buffer and constants, and the first workgroup it owns in the grid.
+struct BatchMember {
+    void *state;
+    int64_t stride;
+    int64_t count;        // points per colour
+    int64_t block_begin;  // first workgroup of this member
+    Coef k;
+    int n;
+    int pad;
+};
+
 // Kernel launchers (kgs_sweep.hip, kgs_energy.hip, kgs_stream3d.hip).  They check the launch
 // shape against the geometry on the host and return hipErrorInvalidValue
 // rather than launch a kernel whose indexing would not fit.
@@ -95,6 +107,13 @@ hipError_t launch_sweep(const Geometry &g, int precision, void *state, int kind,
 bool stream3d_shape_ok(const Geometry &g, const StreamShape &sh, int elem_bytes);
 hipError_t launch_stream3d(const Geometry &g, int precision, const StreamShape &sh, int stages,
                            const void *in, void *out, bool first, const Coef &k, hipStream_t s);
+// Batched sweep over `nm` members (sorted by block_begin, blocks of
+// batch_block() threads).  Kinds: kinds[launch * nm + i] (-1 = idle) if
+// kinds != NULL, else uniform_kind for every member.
+int batch_block();
+hipError_t launch_batch_sweep(int dim, int precision, const BatchMember *members, int nm,
+                              int64_t total_blocks, const int *kinds, int launch,
+                              int uniform_kind, hipStream_t s);
 // Writes the double-double sum of the energy density (without h^dim) to
 // out[0] + out[1] (device memory); `partials` holds 2*energy_partial_slots()
 // doubles.

@@ -46,8 +46,12 @@ __device__ __forceinline__ void uv_update(const Coef &k, double pr, double pi, d
 }
 
 // The point updates of one colour sweep (see PassKind), with the neighbour
-// sums computed once: the other colour does not change within a sweep.
-template <int KIND>
+// sums computed once: the other colour does not change within a sweep.  T is
+// the storage type: the fused red sweep of two consecutive steps rounds the
+// state to T between the steps exactly as storing it at a step boundary
+// would, so a run gives bitwise the same state however its steps are split
+// into calls (float32 state; a no-op for float64).
+template <int KIND, typename T>
 __device__ __forceinline__ void sweep_point(const Coef &k, double &pr, double &pi, double &u,
                                             double &v, double sr, double si, double su)
 {
@@ -65,6 +69,10 @@ __device__ __forceinline__ void sweep_point(const Coef &k, double &pr, double &p
     } else {  // PASS_R_ADJ_BASE
         uv_update(k, pr, pi, u, v, su);
         psi_update(k, pr, pi, u, sr, si);
+        pr = static_cast<double>(static_cast<T>(pr));
+        pi = static_cast<double>(static_cast<T>(pi));
+        u = static_cast<double>(static_cast<T>(u));
+        v = static_cast<double>(static_cast<T>(v));
         psi_update(k, pr, pi, u, sr, si);
         uv_update(k, pr, pi, u, v, su);
     }

@@ -177,11 +177,11 @@ stream3d_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t stride, i
             double pr = own.f[0], pi = own.f[1], u = own.f[2], v = own.f[3];
             if (c == RED) {
                 if (FIRST && j == 0)
-                    sweep_point<PASS_R_BASE>(k, pr, pi, u, v, sum[0], sum[1], sum[2]);
+                    sweep_point<PASS_R_BASE, T>(k, pr, pi, u, v, sum[0], sum[1], sum[2]);
                 else
-                    sweep_point<PASS_R_ADJ_BASE>(k, pr, pi, u, v, sum[0], sum[1], sum[2]);
+                    sweep_point<PASS_R_ADJ_BASE, T>(k, pr, pi, u, v, sum[0], sum[1], sum[2]);
             } else {
-                sweep_point<PASS_B_FULL>(k, pr, pi, u, v, sum[0], sum[1], sum[2]);
+                sweep_point<PASS_B_FULL, T>(k, pr, pi, u, v, sum[0], sum[1], sum[2]);
             }
             Vals<T> res;
             res.f[0] = rnd<T>(pr);

@@ -28,6 +28,8 @@ EXPORTS = (
     "kgs_init", "kgs_step", "kgs_energy", "kgs_read_state", "kgs_write_state", "kgs_sync",
     "kgs_free", "kgs_last_error", "kgs_status_string", "kgs_get_tuning", "kgs_set_tuning",
     "kgs_get_info", "kgs_required_bytes",
+    "kgs_batch_create", "kgs_batch_step", "kgs_batch_step_each", "kgs_batch_set_graph",
+    "kgs_batch_free", "kgs_batch_last_error",
 )
 
 
@@ -91,6 +93,12 @@ def lib():
             "kgs_set_tuning": ([_VP, P(KgsTuning)], ctypes.c_int),
             "kgs_get_info": ([_VP, P(KgsInfo)], ctypes.c_int),
             "kgs_required_bytes": ([P(KgsConfig)], ctypes.c_int64),
+            "kgs_batch_create": ([P(_VP), ctypes.c_int32, _VP, P(_VP)], ctypes.c_int),
+            "kgs_batch_step": ([_VP, ctypes.c_int64], ctypes.c_int),
+            "kgs_batch_step_each": ([_VP, P(ctypes.c_int64)], ctypes.c_int),
+            "kgs_batch_set_graph": ([_VP, ctypes.c_int32], ctypes.c_int),
+            "kgs_batch_free": ([_VP], ctypes.c_int),
+            "kgs_batch_last_error": ([_VP], ctypes.c_char_p),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -303,6 +311,56 @@ class Simulation:
 
     def __exit__(self, *exc):
         self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many simulations advanced together (batched launches, optional hipGraph).
+
+    The batch runs on torch's current stream (the stream the simulations were
+    created on, by default)."""
+
+    def __init__(self, sims, graph: bool = False, stream=None):
+        self.sims = list(sims)
+        arr = (_VP * len(self.sims))(*[s.handle for s in self.sims])
+        self.stream = stream if stream is not None else self.sims[0].stream
+        h = _VP()
+        rc = lib().kgs_batch_create(arr, len(self.sims), self.stream or None, ctypes.byref(h))
+        if rc != KGS_OK:
+            raise KgsError(rc, lib().kgs_batch_last_error(None).decode())
+        self.handle = h
+        if graph:
+            self.set_graph(True)
+
+    def _check(self, rc):
+        if rc != KGS_OK:
+            raise KgsError(rc, lib().kgs_batch_last_error(self.handle).decode())
+
+    def set_graph(self, enable: bool) -> None:
+        self._check(lib().kgs_batch_set_graph(self.handle, int(bool(enable))))
+
+    def step(self, nsteps: int) -> "Batch":
+        self._check(lib().kgs_batch_step(self.handle, int(nsteps)))
+        return self
+
+    def step_each(self, nsteps) -> "Batch":
+        if len(nsteps) != len(self.sims):
+            raise ValueError("one step count per simulation")
+        arr = (ctypes.c_int64 * len(self.sims))(*[int(k) for k in nsteps])
+        self._check(lib().kgs_batch_step_each(self.handle, arr))
+        return self
+
+    def close(self) -> None:
+        if self.handle is not None:
+            h, self.handle = self.handle, None
+            rc = lib().kgs_batch_free(h)
+            if rc != KGS_OK:
+                raise KgsError(rc, "kgs_batch_free")
 
     def __del__(self):
         try:

@@ -186,9 +186,14 @@ def test_launch_shape_does_not_change_results(block):
         assert np.array_equal(a, b)
 
 
-def test_steps_in_chunks_equal_steps_at_once_bitwise():
-    p = workloads.random_problem(2, 40, seed=9, tau=0.05, amp=0.5)
-    say("chunks")
+@pytest.mark.parametrize("dim,n,prec", [(2, 40, workloads.FP64), (2, 40, workloads.FP32),
+                                        (1, 66, workloads.FP32), (3, 64, workloads.FP32),
+                                        (3, 64, workloads.FP64)])
+def test_steps_in_chunks_equal_steps_at_once_bitwise(dim, n, prec):
+    # also for float32 state: the fused red sweep between two steps rounds the
+    # state exactly where a step boundary stores it
+    p = workloads.random_problem(dim, n, seed=9, tau=0.05, amp=0.5, precision=prec)
+    say("chunks", dim, n, prec)
     a = gpu_run(p, 10)
     b = gpu_run(p, 10, chunks=[3, 1, 6])
     for x, y in zip(a, b):
