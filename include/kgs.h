@@ -210,6 +210,85 @@ int kgs_batch_free(kgs_batch *b);
 /* Message of the last failure of b (or of kgs_batch_create for NULL). */
 const char *kgs_batch_last_error(const kgs_batch *b);
 
+/* ------------------------------------------------------------------------
+ * Serving loop with continuous batching.  Requests (any dimension, size,
+ * parameters, precision and step count) are submitted at any time and wait
+ * in arrival order until their device memory fits the budget; running
+ * requests advance together in rounds of up to steps_per_round steps (3-D
+ * float64 requests with their own streaming kernel, all others in one
+ * batched launch sequence), and a request that arrives while others run
+ * joins at the next round.  Finished requests are retired to host memory
+ * and their device memory is freed.  A request's result is bitwise
+ * the state that kgs_step gives when the same simulation runs alone.
+ * Not thread-safe: one thread drives a server.
+ * ---------------------------------------------------------------------- */
+typedef struct kgs_server kgs_server;
+
+enum { KGS_REQ_QUEUED = 0, KGS_REQ_RUNNING = 1, KGS_REQ_DONE = 2, KGS_REQ_FAILED = 3,
+       KGS_REQ_CANCELLED = 4 };
+
+typedef struct {
+    int64_t budget_bytes;    /* device memory the running requests may hold    */
+    int32_t max_active;      /* cap on running requests, 0 = none              */
+    int32_t steps_per_round; /* steps per running request per round, 0 = all  */
+    int32_t reserved[4];     /* must be 0                                      */
+} kgs_server_config;
+
+typedef struct {
+    int32_t state;           /* KGS_REQ_*                                      */
+    int32_t status;          /* KGS_* status of a failed request               */
+    int64_t steps_done, nsteps;
+    int64_t device_bytes;    /* device memory while running                    */
+    double t_submit, t_admit, t_done; /* seconds since kgs_server_create       */
+    double energy_start, energy_end;  /* kgs_energy at admission and at the end */
+} kgs_request_info;
+
+typedef struct {
+    int64_t device_bytes_used;  /* running requests (bounded by the budget)    */
+    int64_t queued_input_bytes; /* device copies of queued device inputs       */
+    int32_t running, queued;
+    int64_t rounds;
+    double now;              /* seconds since kgs_server_create                */
+} kgs_server_stats_t;
+
+/* Create a server whose GPU work is ordered on `stream` (hipStream_t/NULL). */
+int kgs_server_create(const kgs_server_config *cfg, void *stream, kgs_server **out);
+
+/* Queue a request: the initial state (float64 arrays as for kgs_init) is
+ * copied, host inputs into host memory before this call returns, device
+ * inputs into a device buffer held until admission (kgs_server_stats reports
+ * it; it is not part of the running budget) by a copy enqueued on the
+ * server's stream: keep device inputs unchanged until the next
+ * kgs_server_run call has returned.  *id receives the request's handle.
+ * Invalid configurations are rejected here with kgs_init's status. */
+int kgs_server_submit(kgs_server *s, const kgs_config *cfg, const double *psi_re,
+                      const double *psi_im, const double *u, const double *v_t, int32_t mem,
+                      int64_t nsteps, int64_t *id);
+
+/* Run up to `rounds` rounds (admit, advance, retire); returns early when
+ * nothing is left.  Reports how many requests run and wait afterwards. */
+int kgs_server_run(kgs_server *s, int32_t rounds, int32_t *n_running, int32_t *n_queued);
+
+/* State, progress, timestamps and energies of a request. */
+int kgs_server_poll(const kgs_server *s, int64_t id, kgs_request_info *info);
+
+/* Copy the result of a finished request (float64 arrays, host or device). */
+int kgs_server_result(kgs_server *s, int64_t id, double *psi_re, double *psi_im, double *u,
+                      double *v_t, int32_t mem);
+
+/* Forget a request that is not running (its result is dropped). */
+int kgs_server_release(kgs_server *s, int64_t id);
+
+/* Cancel a queued or running request (frees its device memory). */
+int kgs_server_cancel(kgs_server *s, int64_t id);
+
+int kgs_server_stats(const kgs_server *s, kgs_server_stats_t *st);
+
+/* Wait for the server's work and release everything it holds. */
+int kgs_server_free(kgs_server *s);
+
+const char *kgs_server_last_error(const kgs_server *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,7 +30,11 @@ EXPORTS = (
     "kgs_get_info", "kgs_required_bytes",
     "kgs_batch_create", "kgs_batch_step", "kgs_batch_step_each", "kgs_batch_set_graph",
     "kgs_batch_free", "kgs_batch_last_error",
+    "kgs_server_create", "kgs_server_submit", "kgs_server_run", "kgs_server_poll",
+    "kgs_server_result", "kgs_server_release", "kgs_server_cancel", "kgs_server_stats",
+    "kgs_server_free", "kgs_server_last_error",
 )
+KGS_REQ_QUEUED, KGS_REQ_RUNNING, KGS_REQ_DONE, KGS_REQ_FAILED, KGS_REQ_CANCELLED = range(5)
 
 
 class KgsConfig(ctypes.Structure):
@@ -57,6 +61,26 @@ class KgsInfo(ctypes.Structure):
         ("points", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
         ("kernel", ctypes.c_int32), ("precision", ctypes.c_int32),
     ]
+
+
+class KgsServerConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("max_active", ctypes.c_int32),
+                ("steps_per_round", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class KgsRequestInfo(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("steps_done", ctypes.c_int64), ("nsteps", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double),
+                ("energy_start", ctypes.c_double), ("energy_end", ctypes.c_double)]
+
+
+class KgsServerStats(ctypes.Structure):
+    _fields_ = [("device_bytes_used", ctypes.c_int64), ("queued_input_bytes", ctypes.c_int64),
+                ("running", ctypes.c_int32),
+                ("queued", ctypes.c_int32), ("rounds", ctypes.c_int64), ("now", ctypes.c_double)]
 
 
 class KgsError(RuntimeError):
@@ -99,6 +123,19 @@ def lib():
             "kgs_batch_set_graph": ([_VP, ctypes.c_int32], ctypes.c_int),
             "kgs_batch_free": ([_VP], ctypes.c_int),
             "kgs_batch_last_error": ([_VP], ctypes.c_char_p),
+            "kgs_server_create": ([P(KgsServerConfig), _VP, P(_VP)], ctypes.c_int),
+            "kgs_server_submit": ([_VP, P(KgsConfig), _VP, _VP, _VP, _VP, ctypes.c_int32,
+                                   ctypes.c_int64, P(ctypes.c_int64)], ctypes.c_int),
+            "kgs_server_run": ([_VP, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32)],
+                               ctypes.c_int),
+            "kgs_server_poll": ([_VP, ctypes.c_int64, P(KgsRequestInfo)], ctypes.c_int),
+            "kgs_server_result": ([_VP, ctypes.c_int64, _VP, _VP, _VP, _VP, ctypes.c_int32],
+                                  ctypes.c_int),
+            "kgs_server_release": ([_VP, ctypes.c_int64], ctypes.c_int),
+            "kgs_server_cancel": ([_VP, ctypes.c_int64], ctypes.c_int),
+            "kgs_server_stats": ([_VP, P(KgsServerStats)], ctypes.c_int),
+            "kgs_server_free": ([_VP], ctypes.c_int),
+            "kgs_server_last_error": ([_VP], ctypes.c_char_p),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -361,6 +398,96 @@ class Batch:
             rc = lib().kgs_batch_free(h)
             if rc != KGS_OK:
                 raise KgsError(rc, "kgs_batch_free")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving loop with continuous batching (kgs_server_*).  Inputs and
+    results are numpy arrays on the host."""
+
+    def __init__(self, budget_bytes: int, max_active: int = 0, steps_per_round: int = 50,
+                 stream=None):
+        cfg = KgsServerConfig(int(budget_bytes), int(max_active), int(steps_per_round))
+        if stream is None:
+            try:
+                stream = int(_torch().cuda.current_stream().cuda_stream)
+            except Exception:
+                stream = 0
+        self.stream = stream
+        h = _VP()
+        rc = lib().kgs_server_create(ctypes.byref(cfg), stream or None, ctypes.byref(h))
+        if rc != KGS_OK:
+            raise KgsError(rc, lib().kgs_server_last_error(None).decode())
+        self.handle = h
+        self.shapes = {}
+
+    def _check(self, rc):
+        if rc != KGS_OK:
+            raise KgsError(rc, lib().kgs_server_last_error(self.handle).decode())
+
+    def submit(self, cfg: KgsConfig, psi, u, v, nsteps: int) -> int:
+        psi = np.asarray(psi)
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (psi.real, psi.imag, u, v)]
+        rid = ctypes.c_int64()
+        self._check(lib().kgs_server_submit(self.handle, ctypes.byref(cfg),
+                                            *[a.ctypes.data for a in arrs], KGS_HOST,
+                                            int(nsteps), ctypes.byref(rid)))
+        self.shapes[rid.value] = arrs[0].shape
+        return rid.value
+
+    def submit_device(self, cfg: KgsConfig, psi_re, psi_im, u, v, nsteps: int) -> int:
+        """Submit torch cuda float64 tensors (copied on the device)."""
+        rid = ctypes.c_int64()
+        self._check(lib().kgs_server_submit(self.handle, ctypes.byref(cfg), psi_re.data_ptr(),
+                                            psi_im.data_ptr(), u.data_ptr(), v.data_ptr(),
+                                            KGS_DEVICE, int(nsteps), ctypes.byref(rid)))
+        self.shapes[rid.value] = tuple(psi_re.shape)
+        return rid.value
+
+    def submit_problem(self, problem, nsteps=None) -> int:
+        return self.submit(config_of(problem), problem.psi, problem.u, problem.v,
+                           problem.steps if nsteps is None else nsteps)
+
+    def run(self, rounds: int = 1):
+        nr, nq = ctypes.c_int32(), ctypes.c_int32()
+        self._check(lib().kgs_server_run(self.handle, int(rounds), ctypes.byref(nr),
+                                         ctypes.byref(nq)))
+        return nr.value, nq.value
+
+    def poll(self, rid: int) -> KgsRequestInfo:
+        info = KgsRequestInfo()
+        self._check(lib().kgs_server_poll(self.handle, int(rid), ctypes.byref(info)))
+        return info
+
+    def result(self, rid: int):
+        shape = self.shapes[rid]
+        arrs = [np.empty(shape, dtype=np.float64) for _ in range(4)]
+        self._check(lib().kgs_server_result(self.handle, int(rid), *[a.ctypes.data for a in arrs],
+                                            KGS_HOST))
+        P, Q, U, V = arrs
+        return P + 1j * Q, U, V
+
+    def release(self, rid: int) -> None:
+        self._check(lib().kgs_server_release(self.handle, int(rid)))
+        self.shapes.pop(rid, None)
+
+    def cancel(self, rid: int) -> None:
+        self._check(lib().kgs_server_cancel(self.handle, int(rid)))
+
+    def stats(self) -> KgsServerStats:
+        st = KgsServerStats()
+        self._check(lib().kgs_server_stats(self.handle, ctypes.byref(st)))
+        return st
+
+    def close(self) -> None:
+        if self.handle is not None:
+            h, self.handle = self.handle, None
+            lib().kgs_server_free(h)
 
     def __del__(self):
         try:

@@ -37,6 +37,7 @@ class Problem:
     mu: float = 1.0
     gamma: float = 1.0
     precision: int = FP64
+    recipe: object = field(default=None, repr=False)
     psi: Optional[np.ndarray] = field(default=None, repr=False)
     u: Optional[np.ndarray] = field(default=None, repr=False)
     v: Optional[np.ndarray] = field(default=None, repr=False)
@@ -119,26 +120,46 @@ def random_problem(dim: int, n: int, seed: int, tau: float = 0.01, amp: float = 
 
 
 def gaussian_problem(dim: int, n: int, seed: int, lo: float, hi: float, tau: float, steps: int,
-                     precision: int = FP64, params=None) -> Problem:
+                     precision: int = FP64, params=None, arrays: bool = True) -> Problem:
     """Gaussian psi0 and u0 with seeded centres in the middle half of the box,
-    a seeded plane-wave phase, v0 = 0, parameters ~ U[0.5, 2] unless given."""
+    a seeded plane-wave phase, v0 = 0, parameters ~ U[0.5, 2] unless given.
+    With arrays=False only the recipe is drawn (see gaussian_fields_torch)."""
     rng = np.random.default_rng(seed)
     if params is None:
         params = rng.uniform(0.5, 2.0, size=4)
     k1, k2, mu, g = params
     p = Problem(f"gauss{dim}d", dim, n, lo, hi, tau, steps, float(k1), float(k2), float(mu),
                 float(g), precision)
-    X = axes(dim, n, lo, hi)
     half = 0.25 * (hi - lo)
     c_psi = rng.uniform(-half, half, size=dim)
     c_u = rng.uniform(-half, half, size=dim)
     k = rng.uniform(-1.0, 1.0, size=dim)
+    p.recipe = (c_psi, c_u, k)
+    if not arrays:
+        return p
+    X = axes(dim, n, lo, hi)
     r2 = sum((X[a] - c_psi[a]) ** 2 for a in range(dim))
     phase = sum(k[a] * X[a] for a in range(dim))
     p.psi = np.exp(-r2) * np.exp(1j * phase)
     p.u = 0.5 * np.exp(-sum((X[a] - c_u[a]) ** 2 for a in range(dim)))
     p.v = np.zeros_like(X[0])
     return p
+
+
+def gaussian_fields_torch(p: Problem, device="cuda"):
+    """The fields of a gaussian_problem recipe computed on a torch device in
+    float64: (psi_re, psi_im, u, v), each of shape (n,)*dim."""
+    import torch
+
+    c_psi, c_u, k = p.recipe
+    x = p.lo + p.h * torch.arange(p.n, dtype=torch.float64, device=device)
+    X = torch.meshgrid(*([x] * p.dim), indexing="ij")
+    r2 = sum((X[a] - float(c_psi[a])) ** 2 for a in range(p.dim))
+    ph = sum(float(k[a]) * X[a] for a in range(p.dim))
+    amp = torch.exp(-r2)
+    u = 0.5 * torch.exp(-sum((X[a] - float(c_u[a])) ** 2 for a in range(p.dim)))
+    return (amp * torch.cos(ph)).contiguous(), (amp * torch.sin(ph)).contiguous(), u.contiguous(), \
+        torch.zeros_like(u)
 
 
 def batched_instances(count: int = 64, seed: int = 20250213, steps: int = 500,
@@ -168,7 +189,8 @@ class Request:
 
 
 def serving_requests(count: int, rate: float = 50.0, seed: int = 1, max_n=None,
-                     max_steps: int = 2000, min_steps: int = 100) -> List[Request]:
+                     max_steps: int = 2000, min_steps: int = 100,
+                     arrays: bool = True) -> List[Request]:
     """Poisson arrivals (mean `rate` per second) mixing 1-D n in [256, 8192],
     2-D n in [128, 1024], 3-D n in [64, 256] (n even), steps ~ U[min, max],
     precision a fair coin; domains and tau as in the 1-D/2-D/3-D configs.
@@ -188,7 +210,8 @@ def serving_requests(count: int, rate: float = 50.0, seed: int = 1, max_n=None,
         steps = int(rng.integers(min_steps, max_steps + 1))
         prec = int(rng.integers(0, 2))
         lo, hi, tau = boxes[dim]
-        p = gaussian_problem(dim, n, int(rng.integers(1 << 31)), lo, hi, tau, steps, prec)
+        p = gaussian_problem(dim, n, int(rng.integers(1 << 31)), lo, hi, tau, steps, prec,
+                             arrays=arrays)
         p.name = f"req{rid}"
         out.append(Request(rid, t, p))
     return out
