@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--kernel", choices=["auto", "sweep", "stream"], default="auto")
     ap.add_argument("--tile", type=str, default=None,
                     help="stream kernel shape tile_x,tile_y,chunk,steps_per_launch")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the launch configuration with kgs_autotune before timing")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also time a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--requests", type=int, default=120, help="serving: number of requests")
@@ -281,6 +283,8 @@ def main():
         if args.tile:
             t.tile_x, t.tile_y, t.chunk, t.steps_per_launch = (int(v) for v in args.tile.split(","))
         sim.tuning = t
+    if args.autotune:
+        sim.autotune(steps=4, use_cache=False)
     info = sim.info()
     tun = sim.tuning
     sim.step(args.warmup)

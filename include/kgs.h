@@ -139,8 +139,11 @@ enum {
     KGS_KERNEL_STREAM = 2, /* 3-D only: z-streaming kernel, 2 or 4 colour sweeps
                               (1 or 2 full steps) per launch between two state
                               buffers (the handle then holds twice the state) */
-    KGS_KERNEL_RESIDENT = 3, /* 1-D only: whole grid in one workgroup's LDS and
-                                registers, all steps in one launch             */
+    KGS_KERNEL_RESIDENT = 3, /* small grids (at most 4096 points per colour and
+                                6 x points-per-colour x element bytes <= 160 KiB,
+                                e.g. 1-D n <= 6826 float64 / 8192 float32):
+                                the whole grid in one workgroup's LDS and
+                                registers, all steps of a call in one launch */
 };
 
 typedef struct {
@@ -160,6 +163,16 @@ typedef struct {
  * configuration that does not apply to the grid). */
 int kgs_get_tuning(const kgs_sim *sim, kgs_tuning *out);
 int kgs_set_tuning(kgs_sim *sim, const kgs_tuning *t);
+
+/* Autotuner: time each candidate launch configuration that fits the grid
+ * (sweep block sizes; for 3-D grids also streaming tile/chunk shapes with 1
+ * or 2 steps per launch) over `steps` DP-AVF2 steps on the handle's current
+ * state, restore the state after every candidate, and keep the fastest.  The
+ * state is unchanged on return.  With use_cache != 0 a winner found earlier
+ * in this process for the same (dim, n, precision, device) is reused without
+ * timing.  Writes the chosen configuration to *best (may be NULL).  Needs
+ * one extra copy of the state in device memory while it runs. */
+int kgs_autotune(kgs_sim *sim, int32_t steps, int32_t use_cache, kgs_tuning *best);
 
 /* Sizes of a handle: bytes of device memory it holds and the name of the
  * kernel family that kgs_step launches. */

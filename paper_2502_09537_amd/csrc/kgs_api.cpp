@@ -6,6 +6,7 @@
 // with the HIP kernels into libkgs.so.
 #include "kgs.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -21,6 +22,10 @@
 
 
 namespace {
+
+// Longest run of steps in one resident launch (longer runs are split; the
+// result does not depend on the split).
+constexpr int64_t kResidentRun = 1 << 16;
 
 thread_local std::string g_err;
 
@@ -145,10 +150,12 @@ kgs::Geometry make_geometry(const kgs_config &c)
     return g;
 }
 
-// Library default for a grid: the z-streaming kernel with two steps per
-// launch for 3-D float64 states (fastest measured on MI355X for 256^3:
-// 6.4e10 updates/s vs 4.7e10 for one sweep per launch); one sweep per launch
-// otherwise (float32 3-D states run fastest that way: 9.7e10 vs 9.1e10).
+// Library default for a grid: the resident kernel when the grid fits one
+// workgroup (small grids are bound by launch latency otherwise); the
+// z-streaming kernel with two steps per launch for 3-D float64 states
+// (fastest measured on MI355X for 256^3: 6.4e10 updates/s vs 4.7e10 for one
+// sweep per launch); one sweep per launch otherwise (float32 3-D states run
+// fastest that way: 9.7e10 vs 9.1e10).
 kgs_tuning default_tuning(const kgs_config &c)
 {
     kgs_tuning t;
@@ -159,7 +166,11 @@ kgs_tuning default_tuning(const kgs_config &c)
     t.tile_y = 16;
     t.chunk = 128;
     t.steps_per_launch = 2;
-    if (c.dim == 3 && c.precision == KGS_FP64 && c.n >= 64) t.kernel = KGS_KERNEL_STREAM;
+    const kgs::Geometry g = make_geometry(c);
+    if (kgs::resident_fits(g.count, static_cast<int>(elem_bytes(c.precision))))
+        t.kernel = KGS_KERNEL_RESIDENT;
+    else if (c.dim == 3 && c.precision == KGS_FP64 && c.n >= 64)
+        t.kernel = KGS_KERNEL_STREAM;
     return t;
 }
 
@@ -363,6 +374,24 @@ int kgs_step(kgs_sim *s, int64_t nsteps)
         hipError_t e = kgs::launch_sweep(s->geo, prec, s->state, kind, s->coef, block, s->stream);
         return e == hipSuccess ? KGS_OK : hip_fail(s, e, "sweep kernel launch");
     };
+    if (s->tuning.kernel == KGS_KERNEL_RESIDENT) {
+        // one launch per run of at most kResidentRun steps
+        kgs::ResidentMember m;
+        std::memset(&m, 0, sizeof(m));
+        m.state = s->state;
+        m.stride = s->geo.stride;
+        m.k = s->coef;
+        m.n = s->geo.n;
+        m.count = static_cast<int>(s->geo.count);
+        for (int64_t left = nsteps; left > 0;) {
+            m.steps = std::min<int64_t>(left, kResidentRun);
+            hipError_t e = kgs::launch_resident(s->cfg.dim, prec, m, nullptr, nullptr, 0, 1,
+                                                s->geo.count, s->stream);
+            if (e != hipSuccess) return hip_fail(s, e, "resident kernel launch");
+            left -= m.steps;
+        }
+        return KGS_OK;
+    }
     if (s->tuning.kernel == KGS_KERNEL_STREAM) {
         // launches of 1 or 2 full steps (R, B[, R, B]) from one buffer to the
         // other; the adjoint red sweep that closes the last step runs in place
@@ -511,6 +540,9 @@ int kgs_set_tuning(kgs_sim *s, const kgs_tuning *t)
             }
             s->device_bytes += static_cast<int64_t>(8 * s->plane_bytes);
         }
+    } else if (nt.kernel == KGS_KERNEL_RESIDENT) {
+        if (!kgs::resident_fits(s->geo.count, static_cast<int>(elem_bytes(s->cfg.precision))))
+            return fail(s, KGS_EINVAL, "the grid does not fit the resident kernel");
     } else if (nt.kernel != KGS_KERNEL_SWEEP) {
         return fail(s, KGS_EINVAL, "kernel family not available for this grid");
     }

@@ -2,6 +2,9 @@
 // advanced together, one batched launch per colour sweep and per
 // (dimension, storage precision) class instead of one launch per simulation,
 // optionally with the whole step loop captured in a hipGraph and replayed.
+// Members small enough for one workgroup form classes of their own that the
+// resident kernel advances through a whole run in a single launch (one
+// workgroup per member).
 #include <algorithm>
 #include <cstring>
 #include <map>
@@ -19,10 +22,15 @@ namespace {
 
 struct BatchClass {
     int dim = 0, precision = 0;
+    bool resident = false;     // advanced by the resident kernel
     std::vector<int> members;  // indices into kgs_batch::sims
-    kgs::BatchMember *d_members = nullptr;
-    kgs::BatchMember *h_members = nullptr;  // pinned staging
-    int64_t blocks = 0;
+    kgs::BatchMember *d_members = nullptr;    // sweep classes
+    kgs::BatchMember *h_members = nullptr;    // pinned staging
+    kgs::ResidentMember *d_res = nullptr;     // resident classes
+    kgs::ResidentMember *h_res = nullptr;     // pinned staging
+    int64_t blocks = 0;     // sweep classes: workgroups per launch
+    int64_t max_count = 0;  // resident classes: largest member
+    int64_t step_off = 0;   // resident classes: first slot in kgs_batch::d_steps
 };
 
 }  // namespace
@@ -39,6 +47,7 @@ struct kgs_batch {
     std::map<int64_t, hipGraphExec_t> graphs;  // uniform K-step runs
     int *d_kinds = nullptr, *h_kinds = nullptr;  // per-launch member kinds
     int64_t kinds_cap = 0;
+    int64_t *d_steps = nullptr, *h_steps = nullptr;  // per-member steps, resident classes
     std::string err;
 };
 
@@ -69,6 +78,14 @@ void destroy(kgs_batch *b)
         }
         if (c.h_members && hipHostFree(c.h_members) != hipSuccess) {
         }
+        if (c.d_res && hipFree(c.d_res) != hipSuccess) {
+        }
+        if (c.h_res && hipHostFree(c.h_res) != hipSuccess) {
+        }
+    }
+    if (b->d_steps && hipFree(b->d_steps) != hipSuccess) {
+    }
+    if (b->h_steps && hipHostFree(b->h_steps) != hipSuccess) {
     }
     if (b->d_kinds && hipFree(b->d_kinds) != hipSuccess) {
     }
@@ -88,29 +105,50 @@ void destroy(kgs_batch *b)
 // stream before rewriting it.
 int refresh_descriptors(kgs_batch *b)
 {
+    auto held = [&](const BatchClass &c, size_t i) {
+        return c.resident ? c.h_res[i].state : c.h_members[i].state;
+    };
     bool changed = false;
     for (auto &c : b->classes)
         for (size_t i = 0; i < c.members.size(); ++i)
-            changed |= c.h_members[i].state != b->sims[c.members[i]]->state;
+            changed |= held(c, i) != b->sims[c.members[i]]->state;
     if (!changed && b->uploaded) return KGS_OK;
     hipError_t e = hipStreamSynchronize(b->own);
     if (e != hipSuccess) return bhip(b, e, "hipStreamSynchronize");
     for (auto &c : b->classes) {
-        for (size_t i = 0; i < c.members.size(); ++i) c.h_members[i].state = b->sims[c.members[i]]->state;
-        e = hipMemcpyAsync(c.d_members, c.h_members, c.members.size() * sizeof(kgs::BatchMember),
-                           hipMemcpyHostToDevice, b->own);
+        const size_t nm = c.members.size();
+        if (c.resident) {
+            for (size_t i = 0; i < nm; ++i) c.h_res[i].state = b->sims[c.members[i]]->state;
+            e = hipMemcpyAsync(c.d_res, c.h_res, nm * sizeof(kgs::ResidentMember),
+                               hipMemcpyHostToDevice, b->own);
+        } else {
+            for (size_t i = 0; i < nm; ++i) c.h_members[i].state = b->sims[c.members[i]]->state;
+            e = hipMemcpyAsync(c.d_members, c.h_members, nm * sizeof(kgs::BatchMember),
+                               hipMemcpyHostToDevice, b->own);
+        }
         if (e != hipSuccess) return bhip(b, e, "hipMemcpyAsync (batch descriptors)");
     }
     b->uploaded = true;
     return KGS_OK;
 }
 
-// Launch sequence of a uniform K-step run: R_BASE, (B_FULL, R_ADJ_BASE)^(K-1),
-// B_FULL, R_ADJ, each as one batched launch per class.
+// Launch sequence of a uniform K-step run: one resident launch per resident
+// class, then R_BASE, (B_FULL, R_ADJ_BASE)^(K-1), B_FULL, R_ADJ, each as one
+// batched launch per sweep class.
 hipError_t enqueue_uniform(kgs_batch *b, int64_t nsteps)
 {
+    for (auto &c : b->classes) {
+        if (!c.resident) continue;
+        kgs::ResidentMember none;
+        std::memset(&none, 0, sizeof(none));
+        hipError_t e = kgs::launch_resident(c.dim, c.precision, none, c.d_res, nullptr, nsteps,
+                                            static_cast<int>(c.members.size()), c.max_count,
+                                            b->own);
+        if (e != hipSuccess) return e;
+    }
     auto sweep = [&](int kind) {
         for (auto &c : b->classes) {
+            if (c.resident) continue;
             hipError_t e = kgs::launch_batch_sweep(c.dim, c.precision, c.d_members,
                                                    static_cast<int>(c.members.size()), c.blocks,
                                                    nullptr, 0, kind, b->own);
@@ -193,8 +231,11 @@ int kgs_batch_create(kgs_sim *const *sims, int32_t count, void *stream, kgs_batc
         code = bhip(b, e, "hipEventCreate");
     if (code == KGS_OK && (e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming)) != hipSuccess)
         code = bhip(b, e, "hipEventCreate");
-    // group by (dim, precision), larger simulations first
+    // group by (dim, precision, resident), larger simulations first
     if (code == KGS_OK) {
+        auto fits = [](const kgs_sim *s) {
+            return kgs::resident_fits(s->geo.count, s->cfg.precision == KGS_FP64 ? 8 : 4);
+        };
         std::vector<int> order(b->sims.size());
         for (size_t i = 0; i < order.size(); ++i) order[i] = static_cast<int>(i);
         std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
@@ -202,19 +243,48 @@ int kgs_batch_create(kgs_sim *const *sims, int32_t count, void *stream, kgs_batc
         });
         for (int i : order) {
             const kgs_sim *s = b->sims[i];
+            const bool res = fits(s);
             auto it = std::find_if(b->classes.begin(), b->classes.end(), [&](const BatchClass &c) {
-                return c.dim == s->cfg.dim && c.precision == s->cfg.precision;
+                return c.dim == s->cfg.dim && c.precision == s->cfg.precision && c.resident == res;
             });
             if (it == b->classes.end()) {
                 b->classes.emplace_back();
                 it = b->classes.end() - 1;
                 it->dim = s->cfg.dim;
                 it->precision = s->cfg.precision;
+                it->resident = res;
             }
             it->members.push_back(i);
         }
         const int bb = kgs::batch_block();
+        int64_t step_slots = 0;
         for (auto &c : b->classes) {
+            if (c.resident) {
+                const size_t bytes = c.members.size() * sizeof(kgs::ResidentMember);
+                if ((e = hipMalloc(reinterpret_cast<void **>(&c.d_res), bytes)) != hipSuccess) {
+                    code = bhip(b, e, "hipMalloc (batch descriptors)");
+                    break;
+                }
+                if ((e = hipHostMalloc(reinterpret_cast<void **>(&c.h_res), bytes,
+                                       hipHostMallocDefault)) != hipSuccess) {
+                    code = bhip(b, e, "hipHostMalloc (batch descriptors)");
+                    break;
+                }
+                for (size_t i = 0; i < c.members.size(); ++i) {
+                    const kgs_sim *s = b->sims[c.members[i]];
+                    kgs::ResidentMember &m = c.h_res[i];
+                    std::memset(&m, 0, sizeof(m));
+                    m.state = s->state;
+                    m.stride = s->geo.stride;
+                    m.k = s->coef;
+                    m.n = s->geo.n;
+                    m.count = static_cast<int>(s->geo.count);
+                    c.max_count = std::max<int64_t>(c.max_count, s->geo.count);
+                }
+                c.step_off = step_slots;
+                step_slots += static_cast<int64_t>(c.members.size());
+                continue;
+            }
             const size_t bytes = c.members.size() * sizeof(kgs::BatchMember);
             if ((e = hipMalloc(reinterpret_cast<void **>(&c.d_members), bytes)) != hipSuccess) {
                 code = bhip(b, e, "hipMalloc (batch descriptors)");
@@ -243,6 +313,17 @@ int kgs_batch_create(kgs_sim *const *sims, int32_t count, void *stream, kgs_batc
                 break;
             }
             c.blocks = blocks;
+        }
+        if (code == KGS_OK && step_slots > 0) {
+            const size_t bytes = static_cast<size_t>(step_slots) * sizeof(int64_t);
+            if ((e = hipMalloc(reinterpret_cast<void **>(&b->d_steps), bytes)) != hipSuccess)
+                code = bhip(b, e, "hipMalloc (batch steps)");
+            else if ((e = hipHostMalloc(reinterpret_cast<void **>(&b->h_steps), bytes,
+                                        hipHostMallocDefault)) != hipSuccess)
+                code = bhip(b, e, "hipHostMalloc (batch steps)");
+            // kernel attributes are set before any launch can be captured
+            else if ((e = kgs::resident_prepare()) != hipSuccess)
+                code = bhip(b, e, "resident kernel set-up");
         }
     }
     if (code != KGS_OK) {
@@ -310,9 +391,14 @@ int kgs_batch_step_each(kgs_batch *b, const int64_t *nsteps)
     if (kmax == 0) return KGS_OK;
     // launch sequence per class: red 0, blue 0, red 1, ..., blue kmax-1, red kmax
     const int64_t launches = 2 * kmax + 1;
-    size_t nmax = 0;
-    for (auto &c : b->classes) nmax = std::max(nmax, c.members.size());
-    const int64_t need = launches * static_cast<int64_t>(nmax) * static_cast<int64_t>(b->classes.size());
+    size_t nmax = 0, nsweep = 0;
+    for (auto &c : b->classes)
+        if (!c.resident) {
+            nmax = std::max(nmax, c.members.size());
+            ++nsweep;
+        }
+    const int64_t need = std::max<int64_t>(
+        1, launches * static_cast<int64_t>(nmax) * static_cast<int64_t>(nsweep));
     if (need > (int64_t(1) << 31)) return bfail(b, KGS_EINVAL, "schedule too large");
     int rc = begin(b);
     if (rc != KGS_OK) return rc;
@@ -337,11 +423,33 @@ int kgs_batch_step_each(kgs_batch *b, const int64_t *nsteps)
         // pinned staging is reused: wait until the previous schedule was consumed
         return bhip(b, e, "hipStreamSynchronize");
     }
-    // kinds table: [class][launch][member]
+    // steps of the members of resident classes
+    for (auto &c : b->classes)
+        if (c.resident)
+            for (size_t m = 0; m < c.members.size(); ++m)
+                b->h_steps[c.step_off + m] = nsteps[c.members[m]];
+    if (b->d_steps) {
+        int64_t slots = 0;
+        for (auto &c : b->classes)
+            if (c.resident) slots += static_cast<int64_t>(c.members.size());
+        if ((e = hipMemcpyAsync(b->d_steps, b->h_steps, slots * sizeof(int64_t),
+                                hipMemcpyHostToDevice, b->own)) != hipSuccess)
+            return bhip(b, e, "hipMemcpyAsync (steps)");
+        for (auto &c : b->classes) {
+            if (!c.resident) continue;
+            kgs::ResidentMember none;
+            std::memset(&none, 0, sizeof(none));
+            e = kgs::launch_resident(c.dim, c.precision, none, c.d_res, b->d_steps + c.step_off, 0,
+                                     static_cast<int>(c.members.size()), c.max_count, b->own);
+            if (e != hipSuccess) return bhip(b, e, "resident kernel launch");
+        }
+    }
+    // kinds table of the sweep classes: [class][launch][member]
     int64_t off = 0;
     std::vector<int64_t> class_off;
     for (auto &c : b->classes) {
         class_off.push_back(off);
+        if (c.resident) continue;
         const int nm = static_cast<int>(c.members.size());
         for (int64_t L = 0; L < launches; ++L) {
             const int64_t i = L / 2;  // step index
@@ -361,12 +469,14 @@ int kgs_batch_step_each(kgs_batch *b, const int64_t *nsteps)
         }
         off += launches * nm;
     }
+    if (nsweep == 0) return end(b);
     if ((e = hipMemcpyAsync(b->d_kinds, b->h_kinds, off * sizeof(int), hipMemcpyHostToDevice,
                             b->own)) != hipSuccess)
         return bhip(b, e, "hipMemcpyAsync (schedule)");
     for (int64_t L = 0; L < launches; ++L) {
         for (size_t ci = 0; ci < b->classes.size(); ++ci) {
             auto &c = b->classes[ci];
+            if (c.resident) continue;
             e = kgs::launch_batch_sweep(c.dim, c.precision, c.d_members,
                                         static_cast<int>(c.members.size()), c.blocks,
                                         b->d_kinds + class_off[ci], static_cast<int>(L), -1, b->own);

@@ -93,6 +93,22 @@ struct BatchMember {
     int pad;
 };
 
+// One simulation advanced by the resident kernel (kgs_resident.hip): its
+// state buffer, constants, and the number of DP-AVF2 steps to take (<= 0:
+// the member is skipped).
+struct ResidentMember {
+    void *state;
+    int64_t stride;
+    int64_t steps;
+    Coef k;
+    int n;
+    int count;  // points per colour
+};
+
+// Upper bound on the LDS one resident workgroup may use (the device limit
+// can lower it).
+constexpr int kResidentMaxLds = 160 * 1024;
+
 // Kernel launchers (kgs_sweep.hip, kgs_energy.hip, kgs_stream3d.hip).  They check the launch
 // shape against the geometry on the host and return hipErrorInvalidValue
 // rather than launch a kernel whose indexing would not fit.
@@ -114,6 +130,19 @@ int batch_block();
 hipError_t launch_batch_sweep(int dim, int precision, const BatchMember *members, int nm,
                               int64_t total_blocks, const int *kinds, int launch,
                               int uniform_kind, hipStream_t s);
+// Resident kernel: whether a grid of `count` points per colour fits one
+// workgroup; a one-time per-device set-up (LDS limits of the kernel
+// variants; launch_resident calls it, callers that capture launches into a
+// graph call it first); and a launch over one member (list == NULL, nm == 1,
+// one.steps steps) or over the nm members of `list` (device memory, one
+// workgroup each, all of one dimension and precision and each with count <=
+// max_count), member i taking steps_each[i] steps (device memory) or, with
+// steps_each == NULL, steps_all steps.
+bool resident_fits(int64_t count, int elem_bytes);
+hipError_t resident_prepare();
+hipError_t launch_resident(int dim, int precision, const ResidentMember &one,
+                           const ResidentMember *list, const int64_t *steps_each,
+                           int64_t steps_all, int nm, int64_t max_count, hipStream_t s);
 // Writes the double-double sum of the energy density (without h^dim) to
 // out[0] + out[1] (device memory); `partials` holds 2*energy_partial_slots()
 // doubles.

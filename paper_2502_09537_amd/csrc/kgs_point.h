@@ -15,13 +15,26 @@ namespace kgs {
 // scheme, u^{n+1} in the adjoint scheme, where (u,v) is solved first):
 //   (i - c) psi' = (i + c) psi - b S,   c = a - e u,
 // i.e. psi' = num (-c - i) / (1 + c^2) with num = (i + c) psi - b S.
+// 1/x for x >= 1: the hardware reciprocal estimate refined by two
+// Newton-Raphson steps r <- r + r (1 - x r) (each squares the relative
+// error), which leaves the error of the last rounding, within one unit in
+// the last place of the correctly rounded quotient.  x = 1 + c^2 >= 1 rules
+// out the zeros, denormals and overflow that a general division must
+// handle, so the five instructions replace a full IEEE division.
+__device__ __forceinline__ double recip_ge1(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
 __device__ __forceinline__ void psi_update(const Coef &k, double &pr, double &pi, double u,
                                            double sr, double si)
 {
     const double c = fma(-k.e, u, k.a);                // a - e u
     const double nr = fma(-k.b, sr, fma(c, pr, -pi));  // c pr - pi - b sr
     const double ni = fma(-k.b, si, fma(c, pi, pr));   // pr + c pi - b si
-    const double inv = 1.0 / fma(c, c, 1.0);
+    const double inv = recip_ge1(fma(c, c, 1.0));
     pr = fma(-c, nr, ni) * inv;                        // (ni - c nr) / (1 + c^2)
     pi = -fma(c, ni, nr) * inv;                        // -(nr + c ni) / (1 + c^2)
 }

@@ -42,38 +42,154 @@ __device__ __forceinline__ int wrap(int v, int m)
     return v < 0 ? v + m : v;
 }
 
-template <typename T>
-__device__ __forceinline__ T rnd(double x)
-{
-    return static_cast<T>(x);  // rounding of a stored state value
-}
-
-// Largest workgroup per instantiation: the float64 four-sweep pipeline keeps
-// about 60 doubles of FIFO per thread and needs more than 128 VGPRs.
+// Largest workgroup per instantiation: the four-sweep pipeline keeps 16
+// planes of FIFO per thread and needs more than 128 VGPRs.
 template <typename T, int S>
 constexpr int max_threads()
 {
-    return (S == 4 && sizeof(T) == 8) ? 512 : 1024;
+    return S == 4 ? 512 : 1024;
 }
 
-template <typename T, int S, bool FIRST>
+// Per-thread pipeline registers.  Plane FIFOs are rings indexed by the
+// pipeline step modulo 3, so that with the step loop unrolled three times
+// every slot is a fixed register and no value is moved between slots:
+//   R[q % 3]     red level 0, plane loaded at step q (own values of stage 0)
+//   B[q % 3]     blue level 0, plane loaded at step q
+//   F[j][q % 3]  output of stage j (level j + 1) produced at step q
+// Bn holds the blue plane of the next step while B still needs all three
+// slots.
+template <typename T, int S>
+struct Pipe {
+    Vals<T> R[3], B[3], Bn, F[S - 1][3];
+};
+
+// Thread geometry shared by all steps of a workgroup.
+struct Geo {
+    int NT;              // threads with a column of the block
+    bool live, in_tile;  // has a column / writes its column
+    int y;               // wrapped row of the column
+    int64_t col;         // offset of the column inside a plane
+    int i_self, i_ym, i_yp;
+    int i_xm0, i_xm1, i_xp0, i_xp1;  // x-neighbour slots for x-offset o = 0, 1
+};
+
+template <typename T, int S, bool FIRST, int TX, int TY, int PH>
+__device__ __forceinline__ void pipeline_step(Pipe<T, S> &st, const Geo &g, T *lds,
+                                              const T *__restrict__ in, T *__restrict__ out,
+                                              int64_t stride, int64_t plane_elems, int n, int p,
+                                              int steps, int &z_load, const Coef &k)
+{
+    constexpr int HX = (S + 1) / 2, HY = S;
+    const int NT = TX ? (TX + 2 * HX) * (TY + 2 * HY) : g.NT;
+    constexpr int s0 = PH % 3, s1 = (PH + 2) % 3, s2 = (PH + 1) % 3;  // steps p, p-1, p-2
+    // the blue plane of step p arrived in Bn; fetch step p + 1 (red plane
+    // into the slot of step p - 2, which no stage reads any more)
+    st.B[s0] = st.Bn;
+    if (g.live && p + 1 < steps) {
+        const int zn = z_load + 1 == n ? 0 : z_load + 1;
+        const T *pr_ = in + static_cast<int64_t>(zn) * plane_elems + g.col;
+        const T *pb_ = pr_ + 4 * stride;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            st.R[s2].f[q] = pr_[q * stride];
+            st.Bn.f[q] = pb_[q * stride];
+        }
+    }
+    // x-offset of the updated colour in this row: the same for every stage
+    // of the step (the plane moves back by one when the colour flips)
+    const int o = (z_load + g.y + 1) & 1;
+    const int i_xm = o ? g.i_xm1 : g.i_xm0, i_xp = o ? g.i_xp1 : g.i_xp0;
+    const T *pub = lds + static_cast<size_t>((p - 1) & 1) * S * 3 * NT;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        if (p < 2 * j + 2) continue;  // pipeline not yet filled for stage j
+        const int c = j & 1;
+        // level-j neighbours: z -/+ 1 from registers, in-plane from LDS
+        const Vals<T> &up = (j == 0) ? st.B[s0] : st.F[j > 0 ? j - 1 : 0][s0];
+        const Vals<T> &dn = (j == 0) ? st.B[s2] : st.F[j > 0 ? j - 1 : 0][s2];
+        const T *pl0 = pub + j * 3 * NT;
+        double sum[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const T *pl = pl0 + q * NT;
+            double a = static_cast<double>(dn.f[q]);
+            a = a + static_cast<double>(up.f[q]);
+            a = a + static_cast<double>(pl[g.i_ym]);
+            a = a + static_cast<double>(pl[g.i_yp]);
+            a = a + static_cast<double>(pl[i_xm]);
+            a = a + static_cast<double>(pl[i_xp]);
+            sum[q] = a;
+        }
+        // own values at level j: the last output of this colour
+        const Vals<T> &own = (j == 0) ? st.R[s1] : (j == 1) ? st.B[s2] : st.F[j > 1 ? j - 2 : 0][s2];
+        double pr = own.f[0], pi = own.f[1], u = own.f[2], v = own.f[3];
+        if (c == RED) {
+            if (FIRST && j == 0)
+                sweep_point<PASS_R_BASE, T>(k, pr, pi, u, v, sum[0], sum[1], sum[2]);
+            else
+                sweep_point<PASS_R_ADJ_BASE, T>(k, pr, pi, u, v, sum[0], sum[1], sum[2]);
+        } else {
+            sweep_point<PASS_B_FULL, T>(k, pr, pi, u, v, sum[0], sum[1], sum[2]);
+        }
+        Vals<T> res;
+        res.f[0] = static_cast<T>(pr);
+        res.f[1] = static_cast<T>(pi);
+        res.f[2] = static_cast<T>(u);
+        res.f[3] = static_cast<T>(v);
+        if (j < S - 1) {
+            st.F[j < S - 1 ? j : 0][s0] = res;
+        } else if (g.in_tile) {
+            // final level S at plane z: colour c from this stage, the other
+            // colour from stage S-2 one step ago
+            const int z = wrap(z_load - S, n);  // n may be smaller than S
+            const Vals<T> &oth = st.F[S - 2][s1];
+            T *oc = out + static_cast<int64_t>(4 * c) * stride + static_cast<int64_t>(z) * plane_elems + g.col;
+            T *oo = out + static_cast<int64_t>(4 * (c ^ 1)) * stride + static_cast<int64_t>(z) * plane_elems + g.col;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                oc[q * stride] = res.f[q];
+                oo[q * stride] = oth.f[q];
+            }
+        }
+    }
+    z_load = z_load + 1 == n ? 0 : z_load + 1;
+    // publish the newest plane of every level that a stage reads next step
+    if (g.live) {
+        T *pw = lds + static_cast<size_t>(p & 1) * S * 3 * NT;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) pw[q * NT + g.i_self] = st.B[s0].f[q];
+#pragma unroll
+        for (int j = 1; j < S; ++j) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) pw[(j * 3 + q) * NT + g.i_self] = st.F[j - 1][s0].f[q];
+        }
+    }
+    __syncthreads();
+}
+
+// TX, TY > 0: tile shape fixed at compile time (LDS offsets become
+// immediates); 0: taken from the arguments.
+template <typename T, int S, bool FIRST, int TX, int TY>
 __global__ void __launch_bounds__((max_threads<T, S>()))
 stream3d_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t stride, int n,
-                int tiles_x, int tiles_y, int tile_x, int tile_y, int chunk_len, Coef k)
+                int tiles_x, int tiles_y, int tile_x_arg, int tile_y_arg, int chunk_len, Coef k)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *lds = reinterpret_cast<T *>(lds_raw);
 
     constexpr int HX = (S + 1) / 2;
     constexpr int HY = S;
+    const int tile_x = TX ? TX : tile_x_arg;
+    const int tile_y = TY ? TY : tile_y_arg;
     const int H = n >> 1;
     const int BX = tile_x + 2 * HX;
     const int BY = tile_y + 2 * HY;
-    const int NT = BX * BY;
+    Geo g;
+    g.NT = BX * BY;
     const int tid = threadIdx.x;
-    const bool live = tid < NT;
-    const int ltx = live ? tid % BX : 0;
-    const int lty = live ? tid / BX : 0;
+    g.live = tid < g.NT;
+    const int ltx = g.live ? tid % BX : 0;
+    const int lty = g.live ? tid / BX : 0;
 
     // work item: XCD-aware (consecutive items run on the same XCD)
     const int G = gridDim.x;
@@ -90,134 +206,54 @@ stream3d_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t stride, i
     const int xu = x0 - HX + ltx;  // unwrapped compressed x of this thread
     const int yu = y0 - HY + lty;  // unwrapped row
     const int xh = wrap(xu, H);
-    const int y = wrap(yu, n);
-    const bool in_tile = live && ltx >= HX && ltx < HX + tile_x && lty >= HY &&
-                         lty < HY + tile_y && xu < H && yu < n;
+    g.y = wrap(yu, n);
+    g.in_tile = g.live && ltx >= HX && ltx < HX + tile_x && lty >= HY && lty < HY + tile_y &&
+                xu < H && yu < n;
     // in-plane neighbour slots in the block (clamped: edge threads compute
     // values nobody valid depends on)
-    const int i_self = lty * BX + ltx;
-    const int i_ym = max(lty - 1, 0) * BX + ltx;
-    const int i_yp = min(lty + 1, BY - 1) * BX + ltx;
+    g.i_self = lty * BX + ltx;
+    g.i_ym = max(lty - 1, 0) * BX + ltx;
+    g.i_yp = min(lty + 1, BY - 1) * BX + ltx;
+    g.i_xm0 = lty * BX + max(ltx - 1, 0);
+    g.i_xm1 = g.i_self;
+    g.i_xp0 = g.i_self;
+    g.i_xp1 = lty * BX + min(ltx + 1, BX - 1);
 
     const int64_t plane_elems = static_cast<int64_t>(n) * H;
-    const int64_t col = static_cast<int64_t>(y) * H + xh;  // offset inside a plane
-    T *const out_c[2] = {out, out + 4 * stride};
+    g.col = static_cast<int64_t>(g.y) * H + xh;
 
-    // FIFOs (slot 0 = produced at this step): level 0 red (2 slots), level 0
-    // blue (3 slots), levels 1..S-1 (3 slots, colour of the producing stage)
-    Vals<T> r0[2], b0[3], f[S - 1][3];
-    Vals<T> pre_r[2], pre_b[2];  // input planes prefetched two steps ahead
+    Pipe<T, S> st;
     {
         const Vals<T> zero = {{T(0), T(0), T(0), T(0)}};
-        r0[0] = r0[1] = b0[0] = b0[1] = b0[2] = zero;
-        pre_r[0] = pre_r[1] = pre_b[0] = pre_b[1] = zero;
 #pragma unroll
-        for (int j = 0; j < S - 1; ++j) f[j][0] = f[j][1] = f[j][2] = zero;
+        for (int i = 0; i < 3; ++i) {
+            st.R[i] = st.B[i] = zero;
+#pragma unroll
+            for (int j = 0; j < S - 1; ++j) st.F[j][i] = zero;
+        }
+        st.Bn = zero;
     }
-
-    auto load_plane = [&](int z, Vals<T> &rv, Vals<T> &bv) {
-        const T *pr_ = in + static_cast<int64_t>(z) * plane_elems + col;
+    const int steps = L + 2 * S;
+    int z_load = wrap(z0 - S, n);  // plane loaded (consumed) at step p
+    // the first plane: red into the slot of step 0, blue into Bn
+    if (g.live) {
+        const T *pr_ = in + static_cast<int64_t>(z_load) * plane_elems + g.col;
         const T *pb_ = pr_ + 4 * stride;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            rv.f[q] = pr_[q * stride];
-            bv.f[q] = pb_[q * stride];
+            st.R[0].f[q] = pr_[q * stride];
+            st.Bn.f[q] = pb_[q * stride];
         }
-    };
-
-    const int steps = L + 2 * S;
-    // planes are tracked wrapped and advanced by one per step
-    int z_load = wrap(z0 - S, n);  // plane loaded (consumed) at step p
-    int z_pf = z_load;             // next plane to prefetch
-    if (live) load_plane(z_pf, pre_r[0], pre_b[0]);
-    z_pf = z_pf + 1 == n ? 0 : z_pf + 1;
-    if (live && steps > 1) load_plane(z_pf, pre_r[1], pre_b[1]);
-    z_pf = z_pf + 1 == n ? 0 : z_pf + 1;
-
-    for (int p = 0; p < steps; ++p) {
-        const int rb = (p - 1) & 1, wb = p & 1;
-        // shift the level-0 FIFO and take the plane prefetched two steps ago
-        r0[1] = r0[0];
-        b0[2] = b0[1];
-        b0[1] = b0[0];
-        r0[0] = pre_r[0];
-        b0[0] = pre_b[0];
-        pre_r[0] = pre_r[1];
-        pre_b[0] = pre_b[1];
-        if (live && p + 2 < steps) load_plane(z_pf, pre_r[1], pre_b[1]);
-        z_pf = z_pf + 1 == n ? 0 : z_pf + 1;
-
-#pragma unroll
-        for (int j = 0; j < S; ++j) {
-            if (p < 2 * j + 2) continue;  // pipeline not yet filled for stage j
-            const int c = j & 1;
-            int z = z_load - 1 - j;  // plane updated by stage j (wrapped)
-            while (z < 0) z += n;
-            const int o = (z + y + c) & 1;  // x-offset of colour c in this row
-            const int i_xm = lty * BX + max(ltx - 1 + o, 0);
-            const int i_xp = lty * BX + min(ltx + o, BX - 1);
-            // level-j neighbours: z +/- 1 from registers, in-plane from LDS
-            const Vals<T> *upp = (j == 0) ? &b0[0] : &f[max(j - 1, 0)][0];
-            const Vals<T> *dnp = (j == 0) ? &b0[2] : &f[max(j - 1, 0)][2];
-            const T *pub = lds + (static_cast<size_t>(rb) * S + j) * 3 * NT;
-            double sum[3];
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                const T *pl = pub + q * NT;
-                double a = static_cast<double>(dnp->f[q]);
-                a = a + static_cast<double>(upp->f[q]);
-                a = a + static_cast<double>(pl[i_ym]);
-                a = a + static_cast<double>(pl[i_yp]);
-                a = a + static_cast<double>(pl[i_xm]);
-                a = a + static_cast<double>(pl[i_xp]);
-                sum[q] = a;
-            }
-            // own values at level j
-            const Vals<T> &own = (j == 0) ? r0[1] : (j == 1) ? b0[2] : f[max(j - 2, 0)][2];
-            double pr = own.f[0], pi = own.f[1], u = own.f[2], v = own.f[3];
-            if (c == RED) {
-                if (FIRST && j == 0)
-                    sweep_point<PASS_R_BASE, T>(k, pr, pi, u, v, sum[0], sum[1], sum[2]);
-                else
-                    sweep_point<PASS_R_ADJ_BASE, T>(k, pr, pi, u, v, sum[0], sum[1], sum[2]);
-            } else {
-                sweep_point<PASS_B_FULL, T>(k, pr, pi, u, v, sum[0], sum[1], sum[2]);
-            }
-            Vals<T> res;
-            res.f[0] = rnd<T>(pr);
-            res.f[1] = rnd<T>(pi);
-            res.f[2] = rnd<T>(u);
-            res.f[3] = rnd<T>(v);
-            if (j < S - 1) {
-                f[j][2] = f[j][1];
-                f[j][1] = f[j][0];
-                f[j][0] = res;
-            } else if (in_tile) {
-                // final level S at plane z: colour c from this stage, the
-                // other colour from stage S-2 one step ago
-                const Vals<T> &oth = f[S - 2][1];
-                T *oc = out_c[c] + static_cast<int64_t>(z) * plane_elems + col;
-                T *oo = out_c[c ^ 1] + static_cast<int64_t>(z) * plane_elems + col;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    oc[q * stride] = res.f[q];
-                    oo[q * stride] = oth.f[q];
-                }
-            }
-        }
-        z_load = z_load + 1 == n ? 0 : z_load + 1;
-        // publish the newest plane of every level that a stage reads next step
-        if (live) {
-            T *pw = lds + static_cast<size_t>(wb) * S * 3 * NT;
-#pragma unroll
-            for (int q = 0; q < 3; ++q) pw[q * NT + i_self] = b0[0].f[q];
-#pragma unroll
-            for (int j = 1; j < S; ++j) {
-#pragma unroll
-                for (int q = 0; q < 3; ++q) pw[(j * 3 + q) * NT + i_self] = f[j - 1][0].f[q];
-            }
-        }
-        __syncthreads();
+    }
+    const int64_t pe = plane_elems;
+    for (int p = 0; p < steps; p += 3) {
+        pipeline_step<T, S, FIRST, TX, TY, 0>(st, g, lds, in, out, stride, pe, n, p, steps, z_load, k);
+        if (p + 1 < steps)
+            pipeline_step<T, S, FIRST, TX, TY, 1>(st, g, lds, in, out, stride, pe, n, p + 1, steps,
+                                                  z_load, k);
+        if (p + 2 < steps)
+            pipeline_step<T, S, FIRST, TX, TY, 2>(st, g, lds, in, out, stride, pe, n, p + 2, steps,
+                                                  z_load, k);
     }
 }
 
@@ -237,7 +273,13 @@ hipError_t launch_typed(const Geometry &g, const StreamShape &sh, const T *in, T
     const size_t lds = static_cast<size_t>(2) * S * 3 * NT * sizeof(T);
     if (threads > max_threads<T, S>() || items > 0x7fffffff || lds > 160 * 1024)
         return hipErrorInvalidValue;
-    auto kern = first ? stream3d_kernel<T, S, true> : stream3d_kernel<T, S, false>;
+    // the library's default shape for float64 four-sweep launches is
+    // compiled with its tile fixed
+    auto kern = first ? stream3d_kernel<T, S, true, 0, 0> : stream3d_kernel<T, S, false, 0, 0>;
+    if constexpr (sizeof(T) == 8 && S == 4) {
+        if (sh.tile_x == 16 && sh.tile_y == 16)
+            kern = first ? stream3d_kernel<T, S, true, 16, 16> : stream3d_kernel<T, S, false, 16, 16>;
+    }
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(lds));
@@ -258,7 +300,7 @@ bool stream3d_shape_ok(const Geometry &g, const StreamShape &sh, int elem_bytes)
     const int S = 2 * sh.steps;
     const int BX = sh.tile_x + 2 * ((S + 1) / 2), BY = sh.tile_y + 2 * S;
     const int NT = BX * BY;
-    const int limit = (S == 4 && elem_bytes == 8) ? 512 : 1024;
+    const int limit = S == 4 ? 512 : 1024;
     if ((NT + 63) / 64 * 64 > limit) return false;
     return static_cast<size_t>(2) * S * 3 * NT * elem_bytes <= 160 * 1024;
 }

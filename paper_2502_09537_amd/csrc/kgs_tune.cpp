@@ -1,0 +1,135 @@
+// Autotuner: times candidate launch configurations of a simulation on a copy
+// of its current state and keeps the fastest.  Every configuration computes
+// bitwise the same state (same-colour points are independent), so tuning
+// only changes speed; the state is restored after every candidate.  Winners
+// are cached per (dimension, n, precision, device) for the process.
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include <hip/hip_runtime_api.h>
+
+#include "kgs.h"
+#include "kgs_internal.h"
+#include "kgs_sim.h"
+
+namespace {
+
+using Key = std::tuple<int, int, int, int>;  // dim, n, precision, device
+std::map<Key, kgs_tuning> g_cache;
+std::mutex g_cache_mutex;
+
+std::vector<kgs_tuning> candidates(const kgs_sim *s)
+{
+    std::vector<kgs_tuning> out;
+    auto sweep = [&](int block) {
+        kgs_tuning t;
+        std::memset(&t, 0, sizeof(t));
+        t.kernel = KGS_KERNEL_SWEEP;
+        t.block = block;
+        out.push_back(t);
+    };
+    for (int b : {128, 256, 512}) sweep(b);
+    if (s->cfg.dim == 3) {
+        const int eb = s->cfg.precision == KGS_FP32 ? 4 : 8;
+        const int shapes[][4] = {
+            {16, 16, 128, 2}, {16, 17, 64, 2}, {16, 16, 64, 2}, {12, 24, 128, 2}, {8, 32, 128, 2},
+            {32, 16, 64, 2},  {32, 16, 128, 2}, {16, 40, 64, 2}, {32, 16, 64, 1}, {64, 8, 64, 1},
+            {16, 32, 64, 1},  {32, 8, 32, 1},   {16, 16, 32, 2}, {32, 20, 64, 2},
+        };
+        for (const auto &sh : shapes) {
+            kgs::StreamShape ss = {sh[0], sh[1], sh[2], sh[3]};
+            if (!kgs::stream3d_shape_ok(s->geo, ss, eb)) continue;
+            kgs_tuning t;
+            std::memset(&t, 0, sizeof(t));
+            t.kernel = KGS_KERNEL_STREAM;
+            t.block = 256;
+            t.tile_x = sh[0];
+            t.tile_y = sh[1];
+            t.chunk = sh[2];
+            t.steps_per_launch = sh[3];
+            out.push_back(t);
+        }
+    }
+    return out;
+}
+
+}  // namespace
+
+extern "C" int kgs_autotune(kgs_sim *s, int32_t steps, int32_t use_cache, kgs_tuning *best)
+{
+    if (!s || steps < 1) return KGS_EINVAL;
+    const Key key{s->cfg.dim, s->cfg.n, s->cfg.precision, s->device};
+    if (use_cache) {
+        std::lock_guard<std::mutex> lock(g_cache_mutex);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) {
+            int rc = kgs_set_tuning(s, &it->second);
+            if (rc == KGS_OK && best) *best = it->second;
+            return rc;
+        }
+    }
+    if (hipSetDevice(s->device) != hipSuccess) return KGS_EDEVICE;
+    const size_t bytes = 8 * s->plane_bytes;
+    void *backup = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    int rc = KGS_OK;
+    if (hipMalloc(&backup, bytes) != hipSuccess) {
+        s->err = "autotune: no device memory for the state copy";
+        return KGS_ENOMEM;
+    }
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) rc = KGS_EDEVICE;
+    if (rc == KGS_OK &&
+        hipMemcpyAsync(backup, s->state, bytes, hipMemcpyDeviceToDevice, s->stream) != hipSuccess)
+        rc = KGS_EDEVICE;
+    const kgs_tuning original = s->tuning;
+    kgs_tuning winner = original;
+    float best_ms = -1.0f;
+    if (rc == KGS_OK) {
+        for (const kgs_tuning &t : candidates(s)) {
+            if (kgs_set_tuning(s, &t) != KGS_OK) continue;
+            // warm-up step, then `steps` timed steps; restore the state after
+            if (kgs_step(s, 1) != KGS_OK) break;
+            if (hipEventRecord(a, s->stream) != hipSuccess || kgs_step(s, steps) != KGS_OK ||
+                hipEventRecord(b, s->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
+                rc = KGS_EDEVICE;
+                break;
+            }
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+                rc = KGS_EDEVICE;
+                break;
+            }
+            if (best_ms < 0.0f || ms < best_ms) {
+                best_ms = ms;
+                winner = t;
+            }
+            if (hipMemcpyAsync(s->state, backup, bytes, hipMemcpyDeviceToDevice, s->stream) !=
+                hipSuccess) {
+                rc = KGS_EDEVICE;
+                break;
+            }
+        }
+    }
+    if (hipStreamSynchronize(s->stream) != hipSuccess && rc == KGS_OK) rc = KGS_EDEVICE;
+    if (a && hipEventDestroy(a) != hipSuccess) {
+    }
+    if (b && hipEventDestroy(b) != hipSuccess) {
+    }
+    if (hipFree(backup) != hipSuccess) {
+    }
+    if (rc != KGS_OK) {
+        s->err = "autotune: a HIP call failed";
+        kgs_set_tuning(s, &original);
+        return rc;
+    }
+    rc = kgs_set_tuning(s, &winner);
+    if (rc == KGS_OK) {
+        std::lock_guard<std::mutex> lock(g_cache_mutex);
+        g_cache[key] = winner;
+    }
+    if (best) *best = winner;
+    return rc;
+}

@@ -27,7 +27,7 @@ KGS_KERNEL_AUTO, KGS_KERNEL_SWEEP, KGS_KERNEL_STREAM, KGS_KERNEL_RESIDENT = rang
 EXPORTS = (
     "kgs_init", "kgs_step", "kgs_energy", "kgs_read_state", "kgs_write_state", "kgs_sync",
     "kgs_free", "kgs_last_error", "kgs_status_string", "kgs_get_tuning", "kgs_set_tuning",
-    "kgs_get_info", "kgs_required_bytes",
+    "kgs_get_info", "kgs_required_bytes", "kgs_autotune",
     "kgs_batch_create", "kgs_batch_step", "kgs_batch_step_each", "kgs_batch_set_graph",
     "kgs_batch_free", "kgs_batch_last_error",
     "kgs_server_create", "kgs_server_submit", "kgs_server_run", "kgs_server_poll",
@@ -117,6 +117,7 @@ def lib():
             "kgs_set_tuning": ([_VP, P(KgsTuning)], ctypes.c_int),
             "kgs_get_info": ([_VP, P(KgsInfo)], ctypes.c_int),
             "kgs_required_bytes": ([P(KgsConfig)], ctypes.c_int64),
+            "kgs_autotune": ([_VP, ctypes.c_int32, ctypes.c_int32, P(KgsTuning)], ctypes.c_int),
             "kgs_batch_create": ([P(_VP), ctypes.c_int32, _VP, P(_VP)], ctypes.c_int),
             "kgs_batch_step": ([_VP, ctypes.c_int64], ctypes.c_int),
             "kgs_batch_step_each": ([_VP, P(ctypes.c_int64)], ctypes.c_int),
@@ -337,6 +338,13 @@ class Simulation:
 
     def info(self) -> KgsInfo:
         return kgs_get_info(self.handle)
+
+    def autotune(self, steps: int = 4, use_cache: bool = True) -> KgsTuning:
+        """Pick the fastest launch configuration (state unchanged)."""
+        t = KgsTuning()
+        _check(lib().kgs_autotune(self.handle, int(steps), int(bool(use_cache)), ctypes.byref(t)),
+               self.handle)
+        return t
 
     def close(self) -> None:
         if self.handle is not None:

@@ -52,6 +52,8 @@ SHAPES = [
     (6, 3, 2, 3, 2, 2),
     (2, 2, 1, 1, 1, 2),
     (40, 2, 20, 12, 7, 1),
+    (40, 3, 16, 16, 13, 2),   # the compiled-in float64 tile, ragged tiles and chunks
+    (36, 4, 16, 16, 128, 2),  # chunk longer than the grid
 ]
 
 
@@ -105,3 +107,28 @@ def test_default_3d_fp64_uses_streaming_kernel_and_matches_sweep_at_full_size():
     (b, _) = run(p, 2)
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+def test_autotune_keeps_state_and_results():
+    p = workloads.random_problem(3, 66, seed=8, tau=0.03, amp=0.5)
+    say("autotune")
+    sim = kgs.simulation_from_problem(p)
+    before = sim.read_state()
+    best = sim.autotune(steps=2, use_cache=False)
+    after = sim.read_state()
+    for x, y in zip(before, after):
+        assert np.array_equal(x, y)
+    assert sim.tuning.kernel == best.kernel
+    sim.step(3)
+    tuned = sim.read_state()
+    sim.close()
+    (ref, _) = run(p, 3)
+    for x, y in zip(tuned, ref):
+        assert np.array_equal(x, y)
+    # cached winner reused for the same grid
+    sim2 = kgs.simulation_from_problem(p)
+    again = sim2.autotune(steps=2, use_cache=True)
+    assert (again.kernel, again.tile_x, again.tile_y, again.chunk, again.steps_per_launch,
+            again.block) == (best.kernel, best.tile_x, best.tile_y, best.chunk,
+                             best.steps_per_launch, best.block)
+    sim2.close()
