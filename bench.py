@@ -23,7 +23,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_3d256.json")
-KERNEL_SOURCES = ("kgs_stream3d.hip", "kgs_sweep.hip", "kgs_point.h", "kgs_internal.h")
+KERNEL_SOURCES = ("kgs_stream3d.hip", "kgs_sweep.hip", "kgs_sweep_body.h", "kgs_point.h",
+                  "kgs_internal.h")
 ALGO_BYTES = {"fp64": 64, "fp32": 32}  # read + write (P, Q, U, V) once per point-step
 METRIC = "lattice-point updates/s + % HBM roofline (3D 256³ FP64); served p50/p99"
 
@@ -50,6 +51,8 @@ def parse():
     ap.add_argument("--rate", type=float, default=50.0, help="serving: mean arrivals per second")
     ap.add_argument("--budget-gb", type=int, default=64, help="serving: device memory budget")
     ap.add_argument("--round-steps", type=int, default=100, help="serving: steps per round")
+    ap.add_argument("--round-work", type=int, default=0,
+                    help="serving: point-steps per big-grid round (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2,
                     help="oracle steps on the full grid for the CPU baseline")
@@ -192,8 +195,10 @@ def bench_serving(args):
            "config": {"workload": f"serving: {args.requests} Poisson requests at {args.rate}/s, "
                                   "1-D/2-D/3-D mix, fp32/fp64, steps U[100,2000]",
                       "budget_gb": args.budget_gb, "steps_per_round": args.round_steps,
+                      "round_work": args.round_work,
                       "lattice_updates_total": work}}
-    modes = {"continuous": dict(max_active=0, steps_per_round=args.round_steps),
+    modes = {"continuous": dict(max_active=0, steps_per_round=args.round_steps,
+                                round_work=args.round_work),
              "one_at_a_time": dict(max_active=1, steps_per_round=0)}
     check_ids = []
     for mode, kw in modes.items():
@@ -256,6 +261,52 @@ def bench_serving(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_small_dims(args):
+    """The 1-D (n = 256, 1000 steps) and 2-D (n = 1024^2, 1000 steps) float64
+    configurations: updates/s of the library's default kernel for the grid,
+    energy drift over the run, and the oracle on the same grid."""
+    import torch
+
+    from paper_2502_09537_amd import kgs, workloads
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    if args.workload == "1d":
+        p = workloads.config_1d()
+    else:
+        p = workloads.config_2d()
+    steps = args.steps if args.steps is not None else p.steps
+    sim = kgs.simulation_from_problem(p)
+    info = sim.info()
+    sim.step(args.warmup)
+    e0 = sim.energy()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    sim.step(steps)
+    stop.record(stream)
+    e1 = sim.energy()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.close()
+    names = {kgs.KGS_KERNEL_SWEEP: "sweep", kgs.KGS_KERNEL_STREAM: "stream",
+             kgs.KGS_KERNEL_RESIDENT: "resident"}
+    out = {"metric": "lattice-point updates/s", "value": p.points * steps / wall,
+           "unit": "lattice-point updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+           "ms_per_step": wall * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{p.name} n={p.n}^{p.dim} box [{p.lo},{p.hi}) tau={p.tau} "
+                                  f"float64, {steps} DP-AVF2 steps",
+                      "points": p.points, "kernel": names.get(info.kernel, str(info.kernel)),
+                      "parallelism": "1 GPU"},
+           "kernel_ms": start.elapsed_time(stop),
+           "energy_rel_drift": abs(e1 - e0) / abs(e0)}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, steps if p.dim == 1 else 2)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -265,6 +316,8 @@ def main():
         return bench_batched(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload in ("1d", "2d"):
+        return bench_small_dims(args)
     if args.steps is None:
         args.steps = 200
     import torch

@@ -225,14 +225,19 @@ const char *kgs_batch_last_error(const kgs_batch *b);
 
 /* ------------------------------------------------------------------------
  * Serving loop with continuous batching.  Requests (any dimension, size,
- * parameters, precision and step count) are submitted at any time and wait
- * in arrival order until their device memory fits the budget; running
- * requests advance together in rounds of up to steps_per_round steps (3-D
- * float64 requests with their own streaming kernel, all others in one
- * batched launch sequence), and a request that arrives while others run
- * joins at the next round.  Finished requests are retired to host memory
- * and their device memory is freed.  A request's result is bitwise
- * the state that kgs_step gives when the same simulation runs alone.
+ * parameters, precision and step count) are submitted at any time and are
+ * admitted in arrival order while their device memory fits the budget.  Two
+ * lanes share the GPU on streams of their own: grids that fit one workgroup
+ * start together in one persistent resident launch per round and run all
+ * their steps; all other grids advance in rounds of up to steps_per_round
+ * steps, the requests with the least remaining work first, up to round_work
+ * point-steps per round (3-D float64 grids with their own streaming kernel,
+ * the rest in one batched launch sequence).  A request that arrives while
+ * others run joins at the next round.  Finished requests are retired to host
+ * memory and their device memory returns to the server's pool.  Host code
+ * does not wait for the GPU between rounds, except to keep at most two
+ * rounds queued ahead.  A request's result is bitwise the state that
+ * kgs_step gives when the same simulation runs alone.
  * Not thread-safe: one thread drives a server.
  * ---------------------------------------------------------------------- */
 typedef struct kgs_server kgs_server;
@@ -241,10 +246,14 @@ enum { KGS_REQ_QUEUED = 0, KGS_REQ_RUNNING = 1, KGS_REQ_DONE = 2, KGS_REQ_FAILED
        KGS_REQ_CANCELLED = 4 };
 
 typedef struct {
-    int64_t budget_bytes;    /* device memory the running requests may hold    */
+    int64_t budget_bytes;    /* device memory running requests may hold: each
+                                holds kgs_required_bytes plus 32 bytes per point
+                                for its gathered result                        */
     int32_t max_active;      /* cap on running requests, 0 = none              */
     int32_t steps_per_round; /* steps per running request per round, 0 = all  */
-    int32_t reserved[4];     /* must be 0                                      */
+    int64_t round_work;      /* point-steps per round of the big-grid lane,
+                                0 = 2^31 (about 25 ms of float64 3-D work)     */
+    int32_t reserved[2];     /* must be 0                                      */
 } kgs_server_config;
 
 typedef struct {
@@ -271,15 +280,18 @@ int kgs_server_create(const kgs_server_config *cfg, void *stream, kgs_server **o
  * copied, host inputs into host memory before this call returns, device
  * inputs into a device buffer held until admission (kgs_server_stats reports
  * it; it is not part of the running budget) by a copy enqueued on the
- * server's stream: keep device inputs unchanged until the next
- * kgs_server_run call has returned.  *id receives the request's handle.
- * Invalid configurations are rejected here with kgs_init's status. */
+ * server's stream: work the caller orders after it on that stream may
+ * overwrite the inputs.  *id receives the request's handle.  Invalid
+ * configurations are rejected here with kgs_init's status. */
 int kgs_server_submit(kgs_server *s, const kgs_config *cfg, const double *psi_re,
                       const double *psi_im, const double *u, const double *v_t, int32_t mem,
                       int64_t nsteps, int64_t *id);
 
 /* Run up to `rounds` rounds (admit, advance, retire); returns early when
- * nothing is left.  Reports how many requests run and wait afterwards. */
+ * nothing is left.  Reports how many requests are on the device (running or
+ * retiring) and how many wait afterwards.  When nothing is left to enqueue
+ * it waits for the retirements, so a loop that runs until both counts are 0
+ * ends with every request finished. */
 int kgs_server_run(kgs_server *s, int32_t rounds, int32_t *n_running, int32_t *n_queued);
 
 /* State, progress, timestamps and energies of a request. */
@@ -289,10 +301,11 @@ int kgs_server_poll(const kgs_server *s, int64_t id, kgs_request_info *info);
 int kgs_server_result(kgs_server *s, int64_t id, double *psi_re, double *psi_im, double *u,
                       double *v_t, int32_t mem);
 
-/* Forget a request that is not running (its result is dropped). */
+/* Forget a request that is queued or finished (its result is dropped). */
 int kgs_server_release(kgs_server *s, int64_t id);
 
-/* Cancel a queued or running request (frees its device memory). */
+/* Cancel a queued or running request: it reports KGS_REQ_CANCELLED at once;
+ * its device memory returns to the pool after the work already queued. */
 int kgs_server_cancel(kgs_server *s, int64_t id);
 
 int kgs_server_stats(const kgs_server *s, kgs_server_stats_t *st);

@@ -150,12 +150,16 @@ kgs::Geometry make_geometry(const kgs_config &c)
     return g;
 }
 
-// Library default for a grid: the resident kernel when the grid fits one
-// workgroup (small grids are bound by launch latency otherwise); the
-// z-streaming kernel with two steps per launch for 3-D float64 states
-// (fastest measured on MI355X for 256^3: 6.4e10 updates/s vs 4.7e10 for one
-// sweep per launch); one sweep per launch otherwise (float32 3-D states run
-// fastest that way: 9.7e10 vs 9.1e10).
+// Library default for a grid, from measurements on MI355X:
+//  * the resident kernel when the grid fits one workgroup (small grids are
+//    bound by launch latency otherwise);
+//  * for 3-D float64 grids with n >= 96, the z-streaming kernel with two
+//    steps per launch and 16x16 tiles, the chunk of z-planes the longest
+//    power of two (8..128) that still gives about 200 workgroups (256^3:
+//    chunk 128, 9.9e10 updates/s vs 4.7e10 for one sweep per launch; 128^3:
+//    chunk 16, 9.1e10 vs 5.4e10; smaller n run faster with sweeps);
+//  * one sweep per launch otherwise (float32 3-D states run fastest that way
+//    at most sizes: 1.2e11 updates/s at 256^3).
 kgs_tuning default_tuning(const kgs_config &c)
 {
     kgs_tuning t;
@@ -167,10 +171,13 @@ kgs_tuning default_tuning(const kgs_config &c)
     t.chunk = 128;
     t.steps_per_launch = 2;
     const kgs::Geometry g = make_geometry(c);
-    if (kgs::resident_fits(g.count, static_cast<int>(elem_bytes(c.precision))))
+    if (kgs::resident_fits(g.count, static_cast<int>(elem_bytes(c.precision)))) {
         t.kernel = KGS_KERNEL_RESIDENT;
-    else if (c.dim == 3 && c.precision == KGS_FP64 && c.n >= 64)
+    } else if (c.dim == 3 && c.precision == KGS_FP64 && c.n >= 96) {
         t.kernel = KGS_KERNEL_STREAM;
+        const int64_t tiles = static_cast<int64_t>((c.n / 2 + 15) / 16) * ((c.n + 15) / 16);
+        while (t.chunk > 8 && tiles * ((c.n + t.chunk - 1) / t.chunk) < 200) t.chunk /= 2;
+    }
     return t;
 }
 
@@ -212,12 +219,30 @@ void free_device(void *p)
     }
 }
 
+// Device allocation of a handle: from its pool in stream order, or plain.
+hipError_t alloc_device(kgs_sim *s, void **p, size_t bytes)
+{
+    if (s->pool) return hipMallocFromPoolAsync(p, bytes, s->pool, s->stream);
+    return hipMalloc(p, bytes);
+}
+
+void free_handle_memory(kgs_sim *s, void *p)
+{
+    if (!p) return;
+    if (s->pool) {
+        if (hipFreeAsync(p, s->stream) != hipSuccess) {
+        }
+    } else {
+        free_device(p);
+    }
+}
+
 void release(kgs_sim *s)
 {
     if (!s) return;
-    free_device(s->state);
-    free_device(s->state2);
-    free_device(s->partials);
+    free_handle_memory(s, s->state);
+    free_handle_memory(s, s->state2);
+    free_handle_memory(s, s->partials);
     if (s->host_out && hipHostFree(s->host_out) != hipSuccess) {
     }
     s->state = s->state2 = nullptr;
@@ -258,7 +283,124 @@ int load_state(kgs_sim *s, const double *P, const double *Q, const double *U, co
     return KGS_OK;
 }
 
+// A handle for a validated cfg: constants, device memory for the state and
+// the energy partials (from `pool` in stream order when pool != NULL), the
+// padding between planes cleared on the stream.  On failure sets g_err.
+int new_handle(const kgs_config *cfg, hipStream_t stream, hipMemPool_t pool, kgs_sim **out)
+{
+    kgs_sim *s = new (std::nothrow) kgs_sim();
+    if (!s) return fail(nullptr, KGS_ENOMEM, "host allocation failed");
+    s->cfg = *cfg;
+    s->geo = make_geometry(*cfg);
+    s->h = (cfg->hi - cfg->lo) / cfg->n;
+    s->hd = 1.0;
+    for (int a = 0; a < cfg->dim; ++a) s->hd *= s->h;
+    s->coef = half_step_coef(*cfg, s->h);
+    s->ecoef.k1_h2 = cfg->kappa1 / (s->h * s->h);
+    s->ecoef.k2_h2 = cfg->kappa2 / (s->h * s->h);
+    s->ecoef.mu2 = cfg->mu * cfg->mu;
+    s->ecoef.gamma = cfg->gamma;
+    s->stream = stream;
+    s->pool = pool;
+    std::memset(&s->tuning, 0, sizeof(s->tuning));
+    s->tuning.kernel = KGS_KERNEL_SWEEP;
+    s->tuning.block = 256;
+
+    hipError_t e = hipGetDevice(&s->device);
+    if (e != hipSuccess) {
+        hip_fail(s, e, "hipGetDevice");
+        g_err = s->err;
+        delete s;
+        return KGS_EDEVICE;
+    }
+    s->plane_bytes = static_cast<size_t>(s->geo.stride) * elem_bytes(cfg->precision);
+    const size_t partial_bytes = (2 * kgs::energy_partial_slots() + 2) * sizeof(double);
+    int code = KGS_OK;
+    e = alloc_device(s, &s->state, 8 * s->plane_bytes);
+    if (e != hipSuccess) code = hip_fail(s, e, "device allocation (state)");
+    if (code == KGS_OK) {
+        e = alloc_device(s, reinterpret_cast<void **>(&s->partials), partial_bytes);
+        if (e != hipSuccess) code = hip_fail(s, e, "device allocation (energy partials)");
+    }
+    if (code == KGS_OK && !pool) {
+        e = hipHostMalloc(reinterpret_cast<void **>(&s->host_out), 2 * sizeof(double),
+                          hipHostMallocDefault);
+        if (e != hipSuccess) code = hip_fail(s, e, "hipHostMalloc");
+    }
+    if (code == KGS_OK) {
+        // padding between planes is never read by a kernel; clear it anyway
+        e = hipMemsetAsync(s->state, 0, 8 * s->plane_bytes, s->stream);
+        if (e != hipSuccess) code = hip_fail(s, e, "hipMemsetAsync");
+    }
+    if (code != KGS_OK) {
+        g_err = s->err;
+        release(s);
+        delete s;
+        return code;
+    }
+    s->device_bytes = static_cast<int64_t>(8 * s->plane_bytes + partial_bytes);
+    *out = s;
+    return KGS_OK;
+}
+
+// The library's default launch configuration for the handle's grid (the
+// sweep kernel stays if the default shape does not fit).
+void apply_default_tuning(kgs_sim *s)
+{
+    const kgs_tuning dt = default_tuning(s->cfg);
+    if (dt.kernel != KGS_KERNEL_SWEEP) {
+        if (kgs_set_tuning(s, &dt) != KGS_OK) s->err.clear();
+    }
+}
+
 }  // namespace
+
+namespace kgs {
+
+int sim_create_pooled(const kgs_config *cfg, const double *P, const double *Q, const double *U,
+                      const double *V, hipStream_t stream, hipMemPool_t pool, kgs_sim **out,
+                      std::string &err)
+{
+    *out = nullptr;
+    std::string msg;
+    int rc = validate(cfg, msg);
+    if (rc != KGS_OK) {
+        err = msg;
+        return rc;
+    }
+    if (!P || !Q || !U || !V || !pool) {
+        err = "NULL input or pool";
+        return KGS_EINVAL;
+    }
+    kgs_sim *s = nullptr;
+    rc = new_handle(cfg, stream, pool, &s);
+    if (rc != KGS_OK) {
+        err = g_err;
+        return rc;
+    }
+    const hipError_t e = launch_scatter(s->geo, cfg->precision, s->state, P, Q, U, V, stream);
+    if (e != hipSuccess) {
+        rc = hip_fail(s, e, "scatter kernel");
+        err = s->err;
+        release(s);
+        delete s;
+        return rc;
+    }
+    apply_default_tuning(s);
+    *out = s;
+    return KGS_OK;
+}
+
+int default_kernel(const kgs_config &cfg) { return default_tuning(cfg).kernel; }
+
+void sim_destroy_pooled(kgs_sim *s)
+{
+    if (!s) return;
+    release(s);
+    delete s;
+}
+
+}  // namespace kgs
 
 extern "C" {
 
@@ -301,62 +443,17 @@ int kgs_init(const kgs_config *cfg, const double *psi_re, const double *psi_im, 
     if (mem != KGS_HOST && mem != KGS_DEVICE)
         return fail(nullptr, KGS_EINVAL, "mem must be KGS_HOST or KGS_DEVICE");
 
-    kgs_sim *s = new (std::nothrow) kgs_sim();
-    if (!s) return fail(nullptr, KGS_ENOMEM, "host allocation failed");
-    s->cfg = *cfg;
-    s->geo = make_geometry(*cfg);
-    s->h = (cfg->hi - cfg->lo) / cfg->n;
-    s->hd = 1.0;
-    for (int a = 0; a < cfg->dim; ++a) s->hd *= s->h;
-    s->coef = half_step_coef(*cfg, s->h);
-    s->ecoef.k1_h2 = cfg->kappa1 / (s->h * s->h);
-    s->ecoef.k2_h2 = cfg->kappa2 / (s->h * s->h);
-    s->ecoef.mu2 = cfg->mu * cfg->mu;
-    s->ecoef.gamma = cfg->gamma;
-    s->stream = static_cast<hipStream_t>(stream);
-    std::memset(&s->tuning, 0, sizeof(s->tuning));
-    s->tuning.kernel = KGS_KERNEL_SWEEP;
-    s->tuning.block = 256;
-
-    hipError_t e = hipGetDevice(&s->device);
-    if (e != hipSuccess) {
-        hip_fail(s, e, "hipGetDevice");
-        g_err = s->err;
-        delete s;
-        return KGS_EDEVICE;
-    }
-    s->plane_bytes = static_cast<size_t>(s->geo.stride) * elem_bytes(cfg->precision);
-    const size_t partial_bytes = (2 * kgs::energy_partial_slots() + 2) * sizeof(double);
-    int code = KGS_OK;
-    e = hipMalloc(&s->state, 8 * s->plane_bytes);
-    if (e != hipSuccess) code = hip_fail(s, e, "hipMalloc (state)");
-    if (code == KGS_OK) {
-        e = hipMalloc(reinterpret_cast<void **>(&s->partials), partial_bytes);
-        if (e != hipSuccess) code = hip_fail(s, e, "hipMalloc (energy partials)");
-    }
-    if (code == KGS_OK) {
-        e = hipHostMalloc(reinterpret_cast<void **>(&s->host_out), 2 * sizeof(double),
-                          hipHostMallocDefault);
-        if (e != hipSuccess) code = hip_fail(s, e, "hipHostMalloc");
-    }
-    if (code == KGS_OK) {
-        // padding between planes is never read by a kernel; clear it anyway
-        e = hipMemsetAsync(s->state, 0, 8 * s->plane_bytes, s->stream);
-        if (e != hipSuccess) code = hip_fail(s, e, "hipMemsetAsync");
-    }
-    if (code == KGS_OK) code = load_state(s, psi_re, psi_im, u, v_t, mem);
+    kgs_sim *s = nullptr;
+    int code = new_handle(cfg, static_cast<hipStream_t>(stream), nullptr, &s);
+    if (code != KGS_OK) return code;
+    code = load_state(s, psi_re, psi_im, u, v_t, mem);
     if (code != KGS_OK) {
         g_err = s->err;
         release(s);
         delete s;
         return code;
     }
-    s->device_bytes = static_cast<int64_t>(8 * s->plane_bytes + partial_bytes);
-    const kgs_tuning dt = default_tuning(*cfg);
-    if (dt.kernel != KGS_KERNEL_SWEEP) {
-        // falls back to the sweep kernel if the shape does not fit this grid
-        if (kgs_set_tuning(s, &dt) != KGS_OK) s->err.clear();
-    }
+    apply_default_tuning(s);
     *out = s;
     return KGS_OK;
 }
@@ -421,6 +518,7 @@ int kgs_step(kgs_sim *s, int64_t nsteps)
 int kgs_energy(kgs_sim *s, double *energy)
 {
     if (!s || !energy) return fail(s, KGS_EINVAL, "handle or output is NULL");
+    if (!s->host_out) return fail(s, KGS_EINVAL, "handle belongs to a server");
     int rc = check_device(s);
     if (rc != KGS_OK) return rc;
     double *out = s->partials + 2 * kgs::energy_partial_slots();
@@ -533,7 +631,7 @@ int kgs_set_tuning(kgs_sim *s, const kgs_tuning *t)
         if (!s->state2) {
             int rc = check_device(s);
             if (rc != KGS_OK) return rc;
-            hipError_t e = hipMalloc(&s->state2, 8 * s->plane_bytes);
+            hipError_t e = alloc_device(s, &s->state2, 8 * s->plane_bytes);
             if (e != hipSuccess) {
                 s->state2 = nullptr;
                 return hip_fail(s, e, "hipMalloc (second state buffer)");

@@ -1,17 +1,32 @@
 // Serving loop with continuous batching: requests (simulations of any
 // dimension, size, parameters, precision and step count) arrive at any time,
-// wait in a queue, are admitted when their device memory fits the budget,
-// and then advance together in rounds: every running request moves by up to
-// steps_per_round steps per round, 3-D float64 ones with their own
-// z-streaming kernel and all others in one batched run with per-request step
-// counts.  Finished requests are retired (energy and state copied to the
-// host, device memory freed) and queued ones join at the next round.
+// wait in a queue, are admitted in arrival order while their device memory
+// fits the budget, run, and are retired to host memory.
+//
+// Two lanes run side by side on the GPU, each on its own stream:
+//   * small lane: grids that fit one workgroup (the resident kernel).  Each
+//     round, the requests admitted since the last round start together in
+//     one persistent launch per (dimension, precision), each taking all of
+//     its steps, so small requests never wait behind big ones;
+//   * big lane: every other grid, in rounds.  A round advances the running
+//     requests with the least remaining work (points x steps left) first, up
+//     to round_work point-steps per round and steps_per_round steps per
+//     request: 3-D float64 grids with their own z-streaming kernel, the rest
+//     in one batched launch sequence per (dimension, precision) with
+//     per-request step counts.  Shortest-remaining-work-first keeps the mean
+//     and median latency low when the device is oversubscribed.
+// The host does not wait for the GPU in steady state: device memory comes
+// from a private pool in stream order, energies land in pinned slots, a
+// finished request's state is gathered on the device and copied to the host
+// on a copy stream once its event has passed, and at most kMaxAhead rounds
+// are queued ahead of the device on each lane.
 //
 // Each request ends bitwise where running it alone ends: points of one
 // colour are independent and step boundaries store the state exactly as a
 // continuous run's fused sweeps round it.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -28,47 +43,85 @@
 
 namespace {
 
+constexpr int64_t kDefaultRoundWork = int64_t(1) << 31;  // point-steps per big-lane round
+constexpr size_t kMaxAhead = 2;                          // rounds queued ahead, per lane
+constexpr int kRingSlots = 4;                            // staging slots per lane
+constexpr int kSlotChunk = 1024;                         // energy slots per allocation
+
 double now_s()
 {
     using namespace std::chrono;
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
+enum Lane { LANE_BIG = 0, LANE_SMALL = 1 };
+
 struct Request {
     int64_t id = 0;
     kgs_config cfg;
     int64_t nsteps = 0;
-    int64_t done_steps = 0;
+    int64_t done_steps = 0;  // steps enqueued on the device
     int32_t state = KGS_REQ_QUEUED;
     int32_t status = KGS_OK;
-    int64_t bytes = 0;        // device bytes while running
+    int64_t bytes = 0;   // device bytes while running: state + gathered result
     int64_t points = 0;
     double t_submit = 0, t_admit = 0, t_done = 0;
     double e0 = 0, e1 = 0;
-    std::vector<double> host;  // 4 arrays of `points` doubles: host input, then the result
-    double *dev_in = nullptr;  // device copy of a device-submitted input (until admitted)
+    std::unique_ptr<double[]> host;  // 4 arrays of `points` doubles: input, then the result
+    double *dev_in = nullptr;        // pooled device copy of the input until admission
     kgs_sim *sim = nullptr;
+    int lane = LANE_BIG;
+    int slot = -1;                   // energy slot
+    double *staging = nullptr;       // pooled gathered result during retirement
+    hipEvent_t ev = nullptr;         // retirement complete on the device
+    bool retiring = false;
+    bool dropped = false;            // cancelled while retiring
     std::string err;
+};
+
+// Pinned host staging with a device twin, reused round-robin; a slot is
+// rewritten only after the event recorded behind its last reader has passed.
+struct Ring {
+    struct Slot {
+        char *h = nullptr, *d = nullptr;
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;
+        bool used = false;
+    };
+    Slot slots[kRingSlots];
+    int next = 0;
+};
+
+struct EnergyChunk {
+    double *d = nullptr;  // device, 4 doubles per slot: start (hi, lo), end (hi, lo)
+    double *h = nullptr;  // pinned mirror
 };
 
 }  // namespace
 
 struct kgs_server {
     kgs_server_config cfg;
-    hipStream_t stream = nullptr;
+    hipStream_t user = nullptr;  // caller's stream: device input copies
+    hipStream_t lane[2] = {nullptr, nullptr};
+    hipStream_t copy = nullptr;  // host <-> device copies of inputs and results
+    hipMemPool_t pool = nullptr;
+    hipEvent_t ev_submit = nullptr;
+    bool submitted = false;  // device input copies on the caller's stream since the last round
     int device = 0;
     double t0 = 0;
     int64_t next_id = 1;
-    int64_t used = 0;        // device bytes held by running requests
+    int64_t used = 0;        // device bytes held by running and retiring requests
     int64_t queued_dev = 0;  // device bytes held by queued device-submitted inputs
     std::map<int64_t, std::unique_ptr<Request>> reqs;
     std::deque<int64_t> queue;
-    std::vector<int64_t> running;
-    // batch over the running requests that use batched sweeps
-    kgs_batch *batch = nullptr;
-    std::vector<int64_t> batch_ids;
+    std::vector<int64_t> running[2];  // per lane: requests with steps left to enqueue
+    std::vector<int64_t> retiring;    // in order of retirement
+    Ring ring[2];
+    std::vector<EnergyChunk> energy;
+    std::vector<int> free_slots;
+    std::deque<hipEvent_t> ahead;  // one event per queued round and lane
+    std::vector<hipEvent_t> spare_events;
     int64_t rounds = 0;
-    bool pending_copy = false;  // device inputs copied on the stream, not yet waited for
     std::string err;
 };
 
@@ -83,168 +136,581 @@ int sfail(kgs_server *s, int code, const std::string &msg)
     return code;
 }
 
-void release_request(Request *r)
+int shipfail(kgs_server *s, hipError_t e, const char *what)
+{
+    return sfail(s, e == hipErrorOutOfMemory ? KGS_ENOMEM : KGS_EDEVICE,
+                 std::string(what) + ": " + hipGetErrorName(e));
+}
+
+int status_of(hipError_t e) { return e == hipErrorOutOfMemory ? KGS_ENOMEM : KGS_EDEVICE; }
+
+int64_t total_running(const kgs_server *s)
+{
+    return static_cast<int64_t>(s->running[0].size() + s->running[1].size() + s->retiring.size());
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// ---- events -------------------------------------------------------------
+
+hipEvent_t take_event(kgs_server *s)
+{
+    if (!s->spare_events.empty()) {
+        hipEvent_t e = s->spare_events.back();
+        s->spare_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+}
+
+void give_event(kgs_server *s, hipEvent_t e)
+{
+    if (e) s->spare_events.push_back(e);
+}
+
+// ---- energy slots -------------------------------------------------------
+
+int take_slot(kgs_server *s)
+{
+    if (s->free_slots.empty()) {
+        EnergyChunk c;
+        const size_t bytes = 4 * kSlotChunk * sizeof(double);
+        if (hipMalloc(reinterpret_cast<void **>(&c.d), bytes) != hipSuccess) return -1;
+        if (hipHostMalloc(reinterpret_cast<void **>(&c.h), bytes, hipHostMallocDefault) !=
+            hipSuccess) {
+            if (hipFree(c.d) != hipSuccess) {
+            }
+            return -1;
+        }
+        const int base = static_cast<int>(s->energy.size()) * kSlotChunk;
+        s->energy.push_back(c);
+        for (int i = kSlotChunk - 1; i >= 0; --i) s->free_slots.push_back(base + i);
+    }
+    const int slot = s->free_slots.back();
+    s->free_slots.pop_back();
+    return slot;
+}
+
+double *slot_dev(kgs_server *s, int slot, int which)
+{
+    return s->energy[slot / kSlotChunk].d + 4 * (slot % kSlotChunk) + 2 * which;
+}
+
+double *slot_host(kgs_server *s, int slot, int which)
+{
+    return s->energy[slot / kSlotChunk].h + 4 * (slot % kSlotChunk) + 2 * which;
+}
+
+// Energy of the request's current state into part `which` of its slot
+// (0 = start, 1 = end), device -> pinned, in the order of its lane stream.
+hipError_t enqueue_energy(kgs_server *s, Request *r, int which)
+{
+    kgs_sim *m = r->sim;
+    double *d = slot_dev(s, r->slot, which);
+    hipError_t e = kgs::launch_energy(m->geo, m->cfg.precision, m->state, m->ecoef, m->partials, d,
+                                      m->stream);
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(slot_host(s, r->slot, which), d, 2 * sizeof(double),
+                          hipMemcpyDeviceToHost, m->stream);
+}
+
+// ---- staging ring -------------------------------------------------------
+
+// The next slot of a lane's ring with room for `bytes`, its earlier use done.
+Ring::Slot *ring_take(kgs_server *s, int lane, size_t bytes, int &rc)
+{
+    Ring &g = s->ring[lane];
+    Ring::Slot &sl = g.slots[g.next];
+    g.next = (g.next + 1) % kRingSlots;
+    rc = KGS_OK;
+    hipError_t e;
+    if (sl.used && (e = hipEventSynchronize(sl.ev)) != hipSuccess) {
+        rc = shipfail(s, e, "hipEventSynchronize (staging)");
+        return nullptr;
+    }
+    if (sl.cap < bytes) {
+        if (sl.h && hipHostFree(sl.h) != hipSuccess) {
+        }
+        if (sl.d && hipFree(sl.d) != hipSuccess) {
+        }
+        sl.h = sl.d = nullptr;
+        sl.cap = 0;
+        size_t cap = 4096;
+        while (cap < bytes) cap *= 2;
+        if ((e = hipHostMalloc(reinterpret_cast<void **>(&sl.h), cap, hipHostMallocDefault)) !=
+                hipSuccess ||
+            (e = hipMalloc(reinterpret_cast<void **>(&sl.d), cap)) != hipSuccess) {
+            rc = shipfail(s, e, "staging allocation");
+            return nullptr;
+        }
+        sl.cap = cap;
+    }
+    if (!sl.ev && hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess) {
+        rc = sfail(s, KGS_EDEVICE, "hipEventCreate");
+        return nullptr;
+    }
+    return &sl;
+}
+
+// Marks the slot busy until the lane stream has passed its readers.
+hipError_t ring_done(kgs_server *s, int lane, Ring::Slot *sl)
+{
+    sl->used = true;
+    return hipEventRecord(sl->ev, s->lane[lane]);
+}
+
+// ---- request life cycle -------------------------------------------------
+
+// Returns a request's device memory in stream order (after the work queued
+// on the stream each buffer was last used on).
+void free_request_memory(kgs_server *s, Request *r)
 {
     if (r->sim) {
-        if (kgs_free(r->sim) != KGS_OK) {
-        }
+        kgs::sim_destroy_pooled(r->sim);
         r->sim = nullptr;
     }
     if (r->dev_in) {
-        if (hipFree(r->dev_in) != hipSuccess) {
+        if (hipFreeAsync(r->dev_in, s->user) != hipSuccess) {
         }
         r->dev_in = nullptr;
     }
-    std::vector<double>().swap(r->host);
+    if (r->staging) {
+        if (hipFreeAsync(r->staging, s->copy) != hipSuccess) {
+        }
+        r->staging = nullptr;
+    }
 }
 
-bool uses_own_kernel(const kgs_sim *sim) { return sim->tuning.kernel == KGS_KERNEL_STREAM; }
-
-void drop_batch(kgs_server *s)
+void finish(kgs_server *s, Request *r, int32_t state, int32_t status)
 {
-    if (s->batch) {
-        if (kgs_batch_free(s->batch) != KGS_OK) {
-        }
-        s->batch = nullptr;
-    }
-    s->batch_ids.clear();
+    r->state = state;
+    r->status = status;
+    r->t_done = now_s() - s->t0;
 }
 
 // Admit queued requests in arrival order while they fit the budget.
-int admit(kgs_server *s)
+void admit(kgs_server *s)
 {
     while (!s->queue.empty()) {
-        if (s->cfg.max_active > 0 && static_cast<int>(s->running.size()) >= s->cfg.max_active) break;
+        if (s->cfg.max_active > 0 && total_running(s) >= s->cfg.max_active) break;
         Request *r = s->reqs[s->queue.front()].get();
-        // the state plus kgs_init's transient staging copy (host inputs) must fit
-        const int64_t peak =
-            r->bytes + (r->dev_in ? 0 : 4 * r->points * static_cast<int64_t>(sizeof(double)));
-        if (peak > s->cfg.budget_bytes) {
-            s->queue.pop_front();
-            r->state = KGS_REQ_FAILED;
-            r->status = KGS_ENOMEM;
-            r->err = "request needs more device memory than the whole budget";
-            r->t_done = now_s() - s->t0;
-            continue;
-        }
-        if (s->used + peak > s->cfg.budget_bytes) break;  // wait for running ones to retire
-        s->queue.pop_front();
         const int64_t P = r->points;
-        const bool dev = r->dev_in != nullptr;
-        const double *in = dev ? r->dev_in : r->host.data();
-        int rc = kgs_init(&r->cfg, in, in + P, in + 2 * P, in + 3 * P, dev ? KGS_DEVICE : KGS_HOST,
-                          s->stream, &r->sim);
-        if (rc == KGS_OK) {
-            // the input copy is no longer needed
-            if (r->dev_in) {
-                if (hipFree(r->dev_in) != hipSuccess) {
-                }
-                r->dev_in = nullptr;
-                s->queued_dev -= 4 * P * static_cast<int64_t>(sizeof(double));
-            }
-            std::vector<double>().swap(r->host);
-        }
-        if (rc == KGS_OK) rc = kgs_energy(r->sim, &r->e0);
-        if (rc != KGS_OK && rc != KGS_ENONFINITE) {
-            r->err = kgs_last_error(r->sim);
-            if (r->err.empty()) r->err = kgs_last_error(nullptr);
-            if (r->sim) {
-                if (kgs_free(r->sim) != KGS_OK) {
-                }
-                r->sim = nullptr;
-            }
-            if (rc == KGS_ENOMEM) {  // the device is fuller than the budget says: retry later
-                s->queue.push_front(r->id);
-                break;
-            }
-            if (r->dev_in) s->queued_dev -= 4 * r->points * static_cast<int64_t>(sizeof(double));
-            release_request(r);
-            r->state = KGS_REQ_FAILED;
-            r->status = rc;
-            r->t_done = now_s() - s->t0;
+        const size_t in_bytes = 4 * static_cast<size_t>(P) * sizeof(double);
+        if (r->bytes > s->cfg.budget_bytes) {
+            s->queue.pop_front();
+            if (r->dev_in) s->queued_dev -= static_cast<int64_t>(in_bytes);
+            free_request_memory(s, r);
+            r->host.reset();
+            r->err = "request needs more device memory than the whole budget";
+            finish(s, r, KGS_REQ_FAILED, KGS_ENOMEM);
             continue;
         }
+        if (s->used + r->bytes > s->cfg.budget_bytes) break;  // wait for retirements
+        s->queue.pop_front();
+        const int lane = kgs::default_kernel(r->cfg) == KGS_KERNEL_RESIDENT ? LANE_SMALL : LANE_BIG;
+        hipStream_t st = s->lane[lane];
+        hipError_t e = hipSuccess;
+        if (!r->dev_in) {
+            // host input: a pooled device copy made on the copy stream (no
+            // kernels there, so waiting for it waits for the copy only)
+            e = hipMallocFromPoolAsync(reinterpret_cast<void **>(&r->dev_in), in_bytes, s->pool,
+                                       s->copy);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(r->dev_in, r->host.get(), in_bytes, hipMemcpyHostToDevice,
+                                   s->copy);
+            if (e == hipSuccess) e = hipStreamSynchronize(s->copy);
+            r->host.reset();
+        } else {
+            s->queued_dev -= static_cast<int64_t>(in_bytes);
+        }
+        std::string msg;
+        int rc = e == hipSuccess ? KGS_OK : status_of(e);
+        if (rc == KGS_OK)
+            rc = kgs::sim_create_pooled(&r->cfg, r->dev_in, r->dev_in + P, r->dev_in + 2 * P,
+                                        r->dev_in + 3 * P, st, s->pool, &r->sim, msg);
+        else
+            msg = std::string("input copy: ") + hipGetErrorName(e);
+        if (r->dev_in) {
+            if (hipFreeAsync(r->dev_in, st) != hipSuccess) {
+            }
+            r->dev_in = nullptr;
+        }
+        if (rc == KGS_OK && (r->slot = take_slot(s)) < 0) {
+            rc = KGS_ENOMEM;
+            msg = "energy slot allocation failed";
+        }
+        if (rc == KGS_OK && (e = enqueue_energy(s, r, 0)) != hipSuccess) {
+            rc = status_of(e);
+            msg = std::string("energy kernel: ") + hipGetErrorName(e);
+        }
+        if (rc != KGS_OK) {
+            free_request_memory(s, r);
+            r->slot = -1;  // a copy into it may be in flight: not reused
+            r->err = msg;
+            finish(s, r, KGS_REQ_FAILED, rc);
+            continue;
+        }
+        r->lane = lane;
         r->state = KGS_REQ_RUNNING;
         r->t_admit = now_s() - s->t0;
         s->used += r->bytes;
-        s->running.push_back(r->id);
-        drop_batch(s);  // membership changed
+        s->running[lane].push_back(r->id);
     }
+}
+
+// Enqueue the end of a request that took all its steps: the final energy,
+// the state gathered into a pooled float64 buffer, the handle's memory back
+// to the pool, and an event behind them.
+void start_retire(kgs_server *s, Request *r)
+{
+    kgs_sim *m = r->sim;
+    const int64_t P = r->points;
+    const size_t bytes = 4 * static_cast<size_t>(P) * sizeof(double);
+    hipError_t e = enqueue_energy(s, r, 1);
+    if (e == hipSuccess)
+        e = hipMallocFromPoolAsync(reinterpret_cast<void **>(&r->staging), bytes, s->pool,
+                                   m->stream);
+    if (e == hipSuccess)
+        e = kgs::launch_gather(m->geo, m->cfg.precision, m->state, r->staging, r->staging + P,
+                               r->staging + 2 * P, r->staging + 3 * P, m->stream);
+    if (e == hipSuccess && !(r->ev = take_event(s))) e = hipErrorOutOfMemory;
+    if (e == hipSuccess) e = hipEventRecord(r->ev, m->stream);
+    if (e != hipSuccess && r->ev) {
+        give_event(s, r->ev);
+        r->ev = nullptr;
+    }
+    if (e != hipSuccess && r->status == KGS_OK) {
+        r->status = status_of(e);
+        r->err = std::string("retirement: ") + hipGetErrorName(e);
+    }
+    kgs::sim_destroy_pooled(m);  // in stream order: after the gather
+    r->sim = nullptr;
+    r->retiring = true;
+    s->retiring.push_back(r->id);
+}
+
+// Complete a retirement whose event has passed: the result into host
+// memory, the energies from the pinned slot, the device memory released.
+void complete_retire(kgs_server *s, Request *r)
+{
+    int32_t status = r->status;
+    if (status == KGS_OK && !r->dropped) {
+        const size_t n = 4 * static_cast<size_t>(r->points);
+        r->host.reset(new (std::nothrow) double[n]);
+        hipError_t e = r->host ? hipMemcpyAsync(r->host.get(), r->staging, n * sizeof(double),
+                                                hipMemcpyDeviceToHost, s->copy)
+                               : hipErrorOutOfMemory;
+        if (e == hipSuccess) e = hipStreamSynchronize(s->copy);
+        if (e != hipSuccess) {
+            status = status_of(e);
+            r->err = std::string("result copy: ") + hipGetErrorName(e);
+            r->host.reset();
+        }
+    }
+    if (r->slot >= 0) {
+        // h^dim as kgs_energy forms it
+        const double h = (r->cfg.hi - r->cfg.lo) / r->cfg.n;
+        double hd = 1.0;
+        for (int a = 0; a < r->cfg.dim; ++a) hd *= h;
+        const double *h0 = slot_host(s, r->slot, 0), *h1 = slot_host(s, r->slot, 1);
+        r->e0 = hd * (h0[0] + h0[1]);
+        r->e1 = hd * (h1[0] + h1[1]);
+        s->free_slots.push_back(r->slot);
+        r->slot = -1;
+    }
+    if (status == KGS_OK && !(std::isfinite(r->e0) && std::isfinite(r->e1))) {
+        status = KGS_ENONFINITE;
+        r->err = "energy is not finite";
+    }
+    free_request_memory(s, r);
+    give_event(s, r->ev);
+    r->ev = nullptr;
+    r->retiring = false;
+    s->used -= r->bytes;
+    if (r->dropped) r->host.reset();  // already reported as cancelled
+    else finish(s, r, status == KGS_OK ? KGS_REQ_DONE : KGS_REQ_FAILED, status);
+}
+
+// Complete the retirements whose events have passed; with `wait`, all.
+void collect(kgs_server *s, bool wait)
+{
+    std::vector<int64_t> still;
+    for (int64_t id : s->retiring) {
+        Request *r = s->reqs[id].get();
+        hipError_t q = hipSuccess;
+        if (r->ev) q = wait ? hipEventSynchronize(r->ev) : hipEventQuery(r->ev);
+        if (q == hipErrorNotReady) {
+            still.push_back(id);
+            continue;
+        }
+        if (q != hipSuccess && r->status == KGS_OK) {
+            r->status = KGS_EDEVICE;
+            r->err = std::string("retirement event: ") + hipGetErrorName(q);
+        }
+        complete_retire(s, r);
+    }
+    s->retiring.swap(still);
+}
+
+// ---- small lane ---------------------------------------------------------
+
+// One resident launch per (dimension, precision) over the newly admitted
+// small requests, each taking all of its steps; then their retirement.
+int run_small(kgs_server *s)
+{
+    std::vector<int64_t> &ids = s->running[LANE_SMALL];
+    if (ids.empty()) return KGS_OK;
+    std::map<int, std::vector<Request *>> cls;
+    for (int64_t id : ids) {
+        Request *r = s->reqs[id].get();
+        cls[r->cfg.dim * 2 + r->cfg.precision].push_back(r);
+    }
+    size_t bytes = 0;
+    for (auto &kv : cls)
+        bytes += align_up(kv.second.size() * sizeof(kgs::ResidentMember), 256) +
+                 align_up(kv.second.size() * sizeof(int64_t), 256);
+    int rc = KGS_OK;
+    Ring::Slot *sl = ring_take(s, LANE_SMALL, bytes, rc);
+    if (!sl) return rc;
+    struct Launch {
+        int dim, prec, nm;
+        size_t mem_off, steps_off;
+        int64_t max_count;
+    };
+    std::vector<Launch> launches;
+    size_t off = 0;
+    for (auto &kv : cls) {
+        Launch L;
+        L.dim = kv.first / 2;
+        L.prec = kv.first % 2;
+        L.nm = static_cast<int>(kv.second.size());
+        L.mem_off = off;
+        L.max_count = 0;
+        auto *m = reinterpret_cast<kgs::ResidentMember *>(sl->h + off);
+        for (int i = 0; i < L.nm; ++i) {
+            const kgs_sim *x = kv.second[i]->sim;
+            std::memset(&m[i], 0, sizeof(m[i]));
+            m[i].state = x->state;
+            m[i].stride = x->geo.stride;
+            m[i].steps = kv.second[i]->nsteps;
+            m[i].k = x->coef;
+            m[i].n = x->geo.n;
+            m[i].count = static_cast<int>(x->geo.count);
+            L.max_count = std::max<int64_t>(L.max_count, x->geo.count);
+        }
+        off = align_up(off + L.nm * sizeof(kgs::ResidentMember), 256);
+        L.steps_off = off;
+        auto *k = reinterpret_cast<int64_t *>(sl->h + off);
+        for (int i = 0; i < L.nm; ++i) k[i] = kv.second[i]->nsteps;
+        off = align_up(off + L.nm * sizeof(int64_t), 256);
+        launches.push_back(L);
+    }
+    hipError_t e = hipMemcpyAsync(sl->d, sl->h, off, hipMemcpyHostToDevice, s->lane[LANE_SMALL]);
+    for (const Launch &L : launches) {
+        if (e != hipSuccess) break;
+        kgs::ResidentMember none;
+        std::memset(&none, 0, sizeof(none));
+        e = kgs::launch_resident(L.dim, L.prec, none,
+                                 reinterpret_cast<const kgs::ResidentMember *>(sl->d + L.mem_off),
+                                 reinterpret_cast<const int64_t *>(sl->d + L.steps_off), 0, L.nm,
+                                 L.max_count, s->lane[LANE_SMALL]);
+    }
+    const hipError_t e2 = ring_done(s, LANE_SMALL, sl);
+    if (e == hipSuccess) e = e2;
+    for (int64_t id : ids) {
+        Request *r = s->reqs[id].get();
+        r->done_steps = r->nsteps;
+        if (e != hipSuccess) {
+            r->status = status_of(e);
+            r->err = std::string("resident kernel launch: ") + hipGetErrorName(e);
+        }
+        start_retire(s, r);
+    }
+    ids.clear();
     return KGS_OK;
 }
 
-int retire(kgs_server *s, Request *r)
+// ---- big lane -----------------------------------------------------------
+
+// One round: the requests with the least remaining work first, up to the
+// round's work quantum (at least one request).
+int run_big(kgs_server *s)
 {
-    const int64_t P = r->points;
-    int rc = kgs_energy(r->sim, &r->e1);
-    if (rc == KGS_OK || rc == KGS_ENONFINITE) {
-        r->host.assign(static_cast<size_t>(4 * P), 0.0);
-        double *h = r->host.data();
-        rc = kgs_read_state(r->sim, h, h + P, h + 2 * P, h + 3 * P, KGS_HOST);
+    std::vector<int64_t> &ids = s->running[LANE_BIG];
+    if (ids.empty()) return KGS_OK;
+    const int64_t spr = s->cfg.steps_per_round > 0 ? s->cfg.steps_per_round : INT64_MAX;
+    const int64_t quantum = s->cfg.round_work > 0 ? s->cfg.round_work : kDefaultRoundWork;
+    std::vector<Request *> order;
+    for (int64_t id : ids) order.push_back(s->reqs[id].get());
+    std::stable_sort(order.begin(), order.end(), [](const Request *a, const Request *b) {
+        return a->points * (a->nsteps - a->done_steps) < b->points * (b->nsteps - b->done_steps);
+    });
+    std::vector<std::pair<Request *, int64_t>> pick;
+    int64_t work = 0;
+    for (Request *r : order) {
+        const int64_t k = std::min(spr, r->nsteps - r->done_steps);
+        if (!pick.empty() && work + r->points * k > quantum) break;
+        pick.emplace_back(r, k);
+        work += r->points * k;
     }
-    if (rc != KGS_OK) r->err = kgs_last_error(r->sim);
-    if (kgs_free(r->sim) != KGS_OK) {
+    hipStream_t st = s->lane[LANE_BIG];
+    // own-kernel grids now; sweep-kernel grids batched by (dim, precision)
+    std::map<int, std::vector<std::pair<Request *, int64_t>>> cls;
+    for (auto &pk : pick) {
+        Request *r = pk.first;
+        if (pk.second == 0) continue;
+        if (r->sim->tuning.kernel == KGS_KERNEL_STREAM) {
+            if (kgs_step(r->sim, pk.second) != KGS_OK) {
+                r->status = KGS_EDEVICE;
+                r->err = kgs_last_error(r->sim);
+            }
+        } else {
+            cls[r->cfg.dim * 2 + r->cfg.precision].push_back(pk);
+        }
     }
-    r->sim = nullptr;
-    s->used -= r->bytes;
-    r->state = rc == KGS_OK ? KGS_REQ_DONE : KGS_REQ_FAILED;
-    r->status = rc;
-    r->t_done = now_s() - s->t0;
+    if (!cls.empty()) {
+        const int bb = kgs::batch_block();
+        size_t bytes = 0;
+        for (auto &kv : cls) {
+            int64_t kmax = 0;
+            for (auto &pk : kv.second) kmax = std::max(kmax, pk.second);
+            bytes += align_up(kv.second.size() * sizeof(kgs::BatchMember), 256) +
+                     align_up((2 * kmax + 1) * kv.second.size() * sizeof(int), 256);
+        }
+        int rc = KGS_OK;
+        Ring::Slot *sl = ring_take(s, LANE_BIG, bytes, rc);
+        if (!sl) return rc;
+        struct Launch {
+            int dim, prec, nm;
+            size_t mem_off, kinds_off;
+            int64_t blocks, launches;
+        };
+        std::vector<Launch> launches;
+        size_t off = 0;
+        for (auto &kv : cls) {
+            Launch L;
+            L.dim = kv.first / 2;
+            L.prec = kv.first % 2;
+            L.nm = static_cast<int>(kv.second.size());
+            L.mem_off = off;
+            auto *m = reinterpret_cast<kgs::BatchMember *>(sl->h + off);
+            int64_t blocks = 0, kmax = 0;
+            for (int i = 0; i < L.nm; ++i) {
+                const kgs_sim *x = kv.second[i].first->sim;
+                std::memset(&m[i], 0, sizeof(m[i]));
+                m[i].state = x->state;
+                m[i].stride = x->geo.stride;
+                m[i].count = x->geo.count;
+                m[i].block_begin = blocks;
+                m[i].k = x->coef;
+                m[i].n = x->geo.n;
+                blocks += (x->geo.count + bb - 1) / bb;
+                kmax = std::max(kmax, kv.second[i].second);
+            }
+            L.blocks = blocks;
+            off = align_up(off + L.nm * sizeof(kgs::BatchMember), 256);
+            // kinds[launch][member]: red 0, blue 0, red 1, ..., blue k-1, red k
+            L.launches = 2 * kmax + 1;
+            L.kinds_off = off;
+            auto *kinds = reinterpret_cast<int *>(sl->h + off);
+            for (int64_t l = 0; l < L.launches; ++l) {
+                const int64_t i = l / 2;
+                const bool red = (l % 2) == 0;
+                for (int j = 0; j < L.nm; ++j) {
+                    const int64_t k = kv.second[j].second;
+                    int kind = -1;
+                    if (red) {
+                        if (i == 0) kind = kgs::PASS_R_BASE;
+                        else if (i < k) kind = kgs::PASS_R_ADJ_BASE;
+                        else if (i == k) kind = kgs::PASS_R_ADJ;
+                    } else if (i < k) {
+                        kind = kgs::PASS_B_FULL;
+                    }
+                    kinds[l * L.nm + j] = kind;
+                }
+            }
+            off = align_up(off + L.launches * L.nm * sizeof(int), 256);
+            launches.push_back(L);
+        }
+        hipError_t e = hipMemcpyAsync(sl->d, sl->h, off, hipMemcpyHostToDevice, st);
+        for (const Launch &L : launches) {
+            if (e == hipSuccess && L.blocks > 0x7fffffff) e = hipErrorInvalidValue;
+            for (int64_t l = 0; l < L.launches && e == hipSuccess; ++l)
+                e = kgs::launch_batch_sweep(
+                    L.dim, L.prec, reinterpret_cast<const kgs::BatchMember *>(sl->d + L.mem_off),
+                    L.nm, L.blocks, reinterpret_cast<const int *>(sl->d + L.kinds_off),
+                    static_cast<int>(l), -1, st);
+        }
+        const hipError_t e2 = ring_done(s, LANE_BIG, sl);
+        if (e == hipSuccess) e = e2;
+        if (e != hipSuccess)
+            for (auto &kv : cls)
+                for (auto &pk : kv.second) {
+                    pk.first->status = status_of(e);
+                    pk.first->err = std::string("batched sweep launch: ") + hipGetErrorName(e);
+                }
+    }
+    for (auto &pk : pick) pk.first->done_steps += pk.second;
+    std::vector<int64_t> still;
+    for (int64_t id : ids) {
+        Request *r = s->reqs[id].get();
+        if (r->done_steps >= r->nsteps || r->status != KGS_OK) start_retire(s, r);
+        else still.push_back(id);
+    }
+    ids.swap(still);
+    return KGS_OK;
+}
+
+// At most kMaxAhead rounds queued on each lane.
+int throttle(kgs_server *s, const bool used[2])
+{
+    for (int l = 0; l < 2; ++l) {
+        if (!used[l]) continue;
+        hipEvent_t e = take_event(s);
+        if (!e) return sfail(s, KGS_EDEVICE, "hipEventCreate");
+        const hipError_t r = hipEventRecord(e, s->lane[l]);
+        if (r != hipSuccess) {
+            give_event(s, e);
+            return shipfail(s, r, "hipEventRecord (round)");
+        }
+        s->ahead.push_back(e);
+    }
+    while (s->ahead.size() > 2 * kMaxAhead) {
+        hipEvent_t e = s->ahead.front();
+        s->ahead.pop_front();
+        const hipError_t q = hipEventSynchronize(e);
+        give_event(s, e);
+        if (q != hipSuccess) return shipfail(s, q, "hipEventSynchronize (round)");
+    }
     return KGS_OK;
 }
 
 int round_once(kgs_server *s)
 {
+    collect(s, false);
+    if (s->submitted) {
+        // the lanes read device inputs copied on the caller's stream
+        hipError_t e = hipEventRecord(s->ev_submit, s->user);
+        for (int l = 0; l < 2 && e == hipSuccess; ++l)
+            e = hipStreamWaitEvent(s->lane[l], s->ev_submit, 0);
+        if (e != hipSuccess) return shipfail(s, e, "input ordering");
+        s->submitted = false;
+    }
     admit(s);
-    if (s->running.empty()) return KGS_OK;
-    const int64_t spr = s->cfg.steps_per_round > 0 ? s->cfg.steps_per_round : INT64_MAX;
-    // requests on their own kernel
-    std::vector<int64_t> batched;
-    for (int64_t id : s->running) {
-        Request *r = s->reqs[id].get();
-        if (uses_own_kernel(r->sim)) {
-            const int64_t k = std::min(spr, r->nsteps - r->done_steps);
-            int rc = kgs_step(r->sim, k);
-            if (rc != KGS_OK) return sfail(s, rc, kgs_last_error(r->sim));
-            r->done_steps += k;
-        } else {
-            batched.push_back(id);
-        }
+    const bool used[2] = {!s->running[LANE_BIG].empty(), !s->running[LANE_SMALL].empty()};
+    int rc = run_small(s);
+    if (rc == KGS_OK) rc = run_big(s);
+    if (rc != KGS_OK) return rc;
+    if (used[0] || used[1]) {
+        s->rounds++;
+        rc = throttle(s, used);
+        if (rc != KGS_OK) return rc;
+        collect(s, false);
+    } else {
+        collect(s, true);  // nothing left to enqueue: wait for the retirements
     }
-    if (!batched.empty()) {
-        if (!s->batch || s->batch_ids != batched) {
-            drop_batch(s);
-            std::vector<kgs_sim *> sims;
-            for (int64_t id : batched) sims.push_back(s->reqs[id]->sim);
-            int rc = kgs_batch_create(sims.data(), static_cast<int32_t>(sims.size()), s->stream,
-                                      &s->batch);
-            if (rc != KGS_OK) return sfail(s, rc, kgs_batch_last_error(nullptr));
-            s->batch_ids = batched;
-        }
-        std::vector<int64_t> k(batched.size());
-        for (size_t i = 0; i < batched.size(); ++i) {
-            Request *r = s->reqs[batched[i]].get();
-            k[i] = std::min(spr, r->nsteps - r->done_steps);
-            r->done_steps += k[i];
-        }
-        int rc = kgs_batch_step_each(s->batch, k.data());
-        if (rc != KGS_OK) return sfail(s, rc, kgs_batch_last_error(s->batch));
-    }
-    s->rounds++;
-    // retire finished requests (their reads wait for the stream)
-    std::vector<int64_t> still;
-    bool changed = false;
-    for (int64_t id : s->running) {
-        Request *r = s->reqs[id].get();
-        if (r->done_steps >= r->nsteps) {
-            if (!changed) drop_batch(s);  // the batch must not outlive its members
-            changed = true;
-            retire(s, r);
-        } else {
-            still.push_back(id);
-        }
-    }
-    s->running.swap(still);
     return KGS_OK;
 }
 
@@ -259,15 +725,39 @@ int kgs_server_create(const kgs_server_config *cfg, void *stream, kgs_server **o
     if (!out) return sfail(nullptr, KGS_EINVAL, "out is NULL");
     *out = nullptr;
     if (!cfg || cfg->budget_bytes <= 0 || cfg->max_active < 0 || cfg->steps_per_round < 0 ||
-        cfg->reserved[0] || cfg->reserved[1] || cfg->reserved[2] || cfg->reserved[3])
+        cfg->round_work < 0 || cfg->reserved[0] || cfg->reserved[1])
         return sfail(nullptr, KGS_EINVAL, "invalid server configuration");
     kgs_server *s = new (std::nothrow) kgs_server();
     if (!s) return sfail(nullptr, KGS_ENOMEM, "host allocation failed");
     s->cfg = *cfg;
-    s->stream = static_cast<hipStream_t>(stream);
-    if (hipGetDevice(&s->device) != hipSuccess) {
-        delete s;
-        return sfail(nullptr, KGS_EDEVICE, "hipGetDevice failed");
+    s->user = static_cast<hipStream_t>(stream);
+    hipError_t e = hipGetDevice(&s->device);
+    int pools = 0;
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&pools, hipDeviceAttributeMemoryPoolsSupported, s->device);
+    if (e == hipSuccess && !pools) e = hipErrorNotSupported;
+    for (int l = 0; l < 2 && e == hipSuccess; ++l)
+        e = hipStreamCreateWithFlags(&s->lane[l], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_submit, hipEventDisableTiming);
+    if (e == hipSuccess) {
+        hipMemPoolProps props;
+        std::memset(&props, 0, sizeof(props));
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = s->device;
+        e = hipMemPoolCreate(&s->pool, &props);
+    }
+    if (e == hipSuccess) {
+        // keep freed blocks for reuse rather than releasing them at every sync
+        uint64_t keep = UINT64_MAX;
+        e = hipMemPoolSetAttribute(s->pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    if (e != hipSuccess) {
+        const std::string msg = std::string("server set-up: ") + hipGetErrorName(e);
+        kgs_server_free(s);
+        return sfail(nullptr, KGS_EDEVICE, msg);
     }
     s->t0 = now_s();
     *out = s;
@@ -287,7 +777,7 @@ int kgs_server_submit(kgs_server *s, const kgs_config *cfg, const double *psi_re
     if (bytes <= 0) {
         // reuse kgs_init's validation for the message and status
         kgs_sim *tmp = nullptr;
-        int rc = kgs_init(cfg, psi_re, psi_im, u, v_t, mem, s->stream, &tmp);
+        int rc = kgs_init(cfg, psi_re, psi_im, u, v_t, mem, s->user, &tmp);
         if (tmp) kgs_free(tmp);
         return sfail(s, rc != KGS_OK ? rc : KGS_EINVAL, kgs_last_error(nullptr));
     }
@@ -296,34 +786,29 @@ int kgs_server_submit(kgs_server *s, const kgs_config *cfg, const double *psi_re
     r->id = s->next_id++;
     r->cfg = *cfg;
     r->nsteps = nsteps;
-    r->bytes = bytes;
     r->points = 1;
     for (int a = 0; a < cfg->dim; ++a) r->points *= cfg->n;
     const size_t nb = static_cast<size_t>(r->points) * sizeof(double);
+    r->bytes = bytes + static_cast<int64_t>(4 * nb);  // state + gathered result
     const double *src[4] = {psi_re, psi_im, u, v_t};
     if (mem == KGS_HOST) {
-        try {
-            r->host.resize(static_cast<size_t>(4 * r->points));
-        } catch (...) {
-            return sfail(s, KGS_ENOMEM, "host allocation failed");
-        }
-        for (int f = 0; f < 4; ++f) std::memcpy(r->host.data() + f * r->points, src[f], nb);
+        r->host.reset(new (std::nothrow) double[4 * static_cast<size_t>(r->points)]);
+        if (!r->host) return sfail(s, KGS_ENOMEM, "host allocation failed");
+        for (int f = 0; f < 4; ++f) std::memcpy(r->host.get() + f * r->points, src[f], nb);
     } else {
-        // device inputs stay on the device until admission (not counted in
-        // the running budget; see kgs_server_stats)
-        if (hipMalloc(reinterpret_cast<void **>(&r->dev_in), 4 * nb) != hipSuccess) {
-            r->dev_in = nullptr;
-            return sfail(s, KGS_ENOMEM, "device allocation for the queued input failed");
-        }
-        for (int f = 0; f < 4; ++f) {
-            if (hipMemcpyAsync(r->dev_in + f * r->points, src[f], nb, hipMemcpyDeviceToDevice,
-                               s->stream) != hipSuccess) {
-                release_request(r.get());
-                return sfail(s, KGS_EDEVICE, "copy of the initial state failed");
-            }
+        // device inputs: a pooled copy ordered on the caller's stream, held
+        // until admission (reported by kgs_server_stats, outside the budget)
+        hipError_t e = hipMallocFromPoolAsync(reinterpret_cast<void **>(&r->dev_in), 4 * nb,
+                                              s->pool, s->user);
+        for (int f = 0; f < 4 && e == hipSuccess; ++f)
+            e = hipMemcpyAsync(r->dev_in + f * r->points, src[f], nb, hipMemcpyDeviceToDevice,
+                               s->user);
+        if (e != hipSuccess) {
+            free_request_memory(s, r.get());
+            return shipfail(s, e, "device copy of the initial state");
         }
         s->queued_dev += static_cast<int64_t>(4 * nb);
-        s->pending_copy = true;
+        s->submitted = true;
     }
     r->t_submit = now_s() - s->t0;
     *id = r->id;
@@ -336,18 +821,12 @@ int kgs_server_run(kgs_server *s, int32_t rounds, int32_t *n_running, int32_t *n
 {
     if (!s || rounds < 0) return sfail(s, KGS_EINVAL, "bad arguments");
     if (hipSetDevice(s->device) != hipSuccess) return sfail(s, KGS_EDEVICE, "hipSetDevice failed");
-    if (s->pending_copy) {
-        // callers may reuse device inputs once this call returns
-        if (hipStreamSynchronize(s->stream) != hipSuccess)
-            return sfail(s, KGS_EDEVICE, "hipStreamSynchronize failed");
-        s->pending_copy = false;
-    }
     for (int32_t i = 0; i < rounds; ++i) {
         int rc = round_once(s);
         if (rc != KGS_OK) return rc;
-        if (s->running.empty() && s->queue.empty()) break;
+        if (total_running(s) == 0 && s->queue.empty()) break;
     }
-    if (n_running) *n_running = static_cast<int32_t>(s->running.size());
+    if (n_running) *n_running = static_cast<int32_t>(total_running(s));
     if (n_queued) *n_queued = static_cast<int32_t>(s->queue.size());
     return KGS_OK;
 }
@@ -379,13 +858,13 @@ int kgs_server_result(kgs_server *s, int64_t id, double *psi_re, double *psi_im,
     auto it = s->reqs.find(id);
     if (it == s->reqs.end()) return sfail(s, KGS_EINVAL, "unknown request");
     Request *r = it->second.get();
-    if (r->state != KGS_REQ_DONE) return sfail(s, KGS_EINVAL, "request has no result");
+    if (r->state != KGS_REQ_DONE || !r->host) return sfail(s, KGS_EINVAL, "request has no result");
     if (!psi_re || !psi_im || !u || !v_t || (mem != KGS_HOST && mem != KGS_DEVICE))
         return sfail(s, KGS_EINVAL, "bad output arguments");
     const size_t nb = static_cast<size_t>(r->points) * sizeof(double);
     double *dst[4] = {psi_re, psi_im, u, v_t};
     for (int f = 0; f < 4; ++f) {
-        const double *src = r->host.data() + f * r->points;
+        const double *src = r->host.get() + f * r->points;
         if (mem == KGS_HOST) std::memcpy(dst[f], src, nb);
         else if (hipMemcpy(dst[f], src, nb, hipMemcpyHostToDevice) != hipSuccess)
             return sfail(s, KGS_EDEVICE, "copy of the result failed");
@@ -399,12 +878,13 @@ int kgs_server_release(kgs_server *s, int64_t id)
     auto it = s->reqs.find(id);
     if (it == s->reqs.end()) return sfail(s, KGS_EINVAL, "unknown request");
     Request *r = it->second.get();
-    if (r->state == KGS_REQ_RUNNING) return sfail(s, KGS_EINVAL, "request is running");
+    if (r->state == KGS_REQ_RUNNING || r->retiring)
+        return sfail(s, KGS_EINVAL, "request is still on the device");
     if (r->state == KGS_REQ_QUEUED) {
         s->queue.erase(std::find(s->queue.begin(), s->queue.end(), id));
         if (r->dev_in) s->queued_dev -= 4 * r->points * static_cast<int64_t>(sizeof(double));
     }
-    release_request(r);
+    free_request_memory(s, r);
     s->reqs.erase(it);
     return KGS_OK;
 }
@@ -418,17 +898,25 @@ int kgs_server_cancel(kgs_server *s, int64_t id)
     if (r->state == KGS_REQ_QUEUED) {
         s->queue.erase(std::find(s->queue.begin(), s->queue.end(), id));
         if (r->dev_in) s->queued_dev -= 4 * r->points * static_cast<int64_t>(sizeof(double));
-    } else if (r->state == KGS_REQ_RUNNING) {
-        drop_batch(s);
-        if (hipStreamSynchronize(s->stream) != hipSuccess) return sfail(s, KGS_EDEVICE, "sync failed");
-        s->running.erase(std::find(s->running.begin(), s->running.end(), id));
-        s->used -= r->bytes;
-    } else {
-        return sfail(s, KGS_EINVAL, "request already finished");
+        free_request_memory(s, r);
+        r->host.reset();
+        finish(s, r, KGS_REQ_CANCELLED, KGS_OK);
+        return KGS_OK;
     }
-    release_request(r);
-    r->state = KGS_REQ_CANCELLED;
-    r->t_done = now_s() - s->t0;
+    if (r->state != KGS_REQ_RUNNING) return sfail(s, KGS_EINVAL, "request already finished");
+    if (r->retiring) {
+        // its device work ends at the next collection; the result is dropped
+        r->dropped = true;
+        finish(s, r, KGS_REQ_CANCELLED, KGS_OK);
+        return KGS_OK;
+    }
+    // work already queued for the request stays ordered before its memory's return
+    std::vector<int64_t> &lane = s->running[r->lane];
+    lane.erase(std::find(lane.begin(), lane.end(), id));
+    free_request_memory(s, r);
+    r->slot = -1;  // its start energy may still be in flight into the slot: not reused
+    s->used -= r->bytes;
+    finish(s, r, KGS_REQ_CANCELLED, KGS_OK);
     return KGS_OK;
 }
 
@@ -438,7 +926,7 @@ int kgs_server_stats(const kgs_server *s, kgs_server_stats_t *st)
     std::memset(st, 0, sizeof(*st));
     st->device_bytes_used = s->used;
     st->queued_input_bytes = s->queued_dev;
-    st->running = static_cast<int32_t>(s->running.size());
+    st->running = static_cast<int32_t>(total_running(s));
     st->queued = static_cast<int32_t>(s->queue.size());
     st->rounds = s->rounds;
     st->now = now_s() - s->t0;
@@ -448,9 +936,38 @@ int kgs_server_stats(const kgs_server *s, kgs_server_stats_t *st)
 int kgs_server_free(kgs_server *s)
 {
     if (!s) return KGS_OK;
-    drop_batch(s);
-    int rc = hipStreamSynchronize(s->stream) == hipSuccess ? KGS_OK : KGS_EDEVICE;
-    for (auto &kv : s->reqs) release_request(kv.second.get());
+    int rc = KGS_OK;
+    if (hipSetDevice(s->device) != hipSuccess) rc = KGS_EDEVICE;
+    collect(s, true);
+    for (auto &kv : s->reqs) free_request_memory(s, kv.second.get());
+    for (hipStream_t st : {s->lane[0], s->lane[1], s->copy})
+        if (st && hipStreamSynchronize(st) != hipSuccess) rc = KGS_EDEVICE;
+    if (hipStreamSynchronize(s->user) != hipSuccess) rc = KGS_EDEVICE;
+    for (hipEvent_t e : s->ahead) give_event(s, e);
+    for (hipEvent_t e : s->spare_events)
+        if (hipEventDestroy(e) != hipSuccess) {
+        }
+    for (auto &g : s->ring)
+        for (auto &sl : g.slots) {
+            if (sl.h && hipHostFree(sl.h) != hipSuccess) {
+            }
+            if (sl.d && hipFree(sl.d) != hipSuccess) {
+            }
+            if (sl.ev && hipEventDestroy(sl.ev) != hipSuccess) {
+            }
+        }
+    for (auto &c : s->energy) {
+        if (c.d && hipFree(c.d) != hipSuccess) {
+        }
+        if (c.h && hipHostFree(c.h) != hipSuccess) {
+        }
+    }
+    if (s->ev_submit && hipEventDestroy(s->ev_submit) != hipSuccess) {
+    }
+    for (hipStream_t st : {s->lane[0], s->lane[1], s->copy})
+        if (st && hipStreamDestroy(st) != hipSuccess) {
+        }
+    if (s->pool && hipMemPoolDestroy(s->pool) != hipSuccess) rc = KGS_EDEVICE;
     delete s;
     return rc;
 }

@@ -21,10 +21,28 @@ struct kgs_sim {
     void *state2 = nullptr; // second copy for ping-pong kernels (3-D streaming)
     size_t plane_bytes = 0;
     double *partials = nullptr;  // energy partials, then the 2-double result
-    double *host_out = nullptr;  // pinned, 2 doubles
+    double *host_out = nullptr;  // pinned, 2 doubles (not held by pooled handles)
+    hipMemPool_t pool = nullptr; // device memory comes from this pool in stream order
     hipStream_t stream = nullptr;
     int device = 0;
     kgs_tuning tuning;
     int64_t device_bytes = 0;
     std::string err;
 };
+
+namespace kgs {
+
+// Handles for the server: device memory from `pool` in the order of `stream`
+// (no host synchronisation anywhere), initial state from float64 device
+// arrays read by a scatter kernel on the stream, the library's default
+// launch configuration.  kgs_step / kgs_set_tuning work on such handles;
+// kgs_energy does not (the caller launches the energy kernel itself).
+int sim_create_pooled(const kgs_config *cfg, const double *P, const double *Q, const double *U,
+                      const double *V, hipStream_t stream, hipMemPool_t pool, kgs_sim **out,
+                      std::string &err);
+// Returns the memory to the pool in stream order after all queued work.
+void sim_destroy_pooled(kgs_sim *s);
+// KGS_KERNEL_* that a new handle for cfg (valid) runs by default.
+int default_kernel(const kgs_config &cfg);
+
+}  // namespace kgs

@@ -66,12 +66,63 @@ struct Pipe {
 // Thread geometry shared by all steps of a workgroup.
 struct Geo {
     int NT;              // threads with a column of the block
+    int wave;            // first thread of this thread's wave
+    int need[5];         // stage j runs on threads below need[S - 1 - j]
     bool live, in_tile;  // has a column / writes its column
     int y;               // wrapped row of the column
     int64_t col;         // offset of the column inside a plane
     int i_self, i_ym, i_yp;
     int i_xm0, i_xm1, i_xp0, i_xp1;  // x-neighbour slots for x-offset o = 0, 1
 };
+
+// Threads are ordered by concentric rings around the output tile, so that
+// the columns each sweep stage needs are the first threads of the
+// workgroup and whole waves can skip a stage.  R(m) is the tile grown by m
+// rows and ceil(m/2) compressed positions on every side: the columns a
+// stage with m sweeps still to follow must update (each sweep reaches one
+// point further along every axis, i.e. half a compressed position in x).
+// R(S) is the whole block.  Ring m = R(m) minus R(m-1) is enumerated as its
+// top row, bottom row, left column, right column.
+__device__ __forceinline__ int ring_x(int m) { return (m + 1) >> 1; }
+
+template <int S>
+__device__ __forceinline__ int ring_area(int m, int tile_x, int tile_y)
+{
+    return (tile_x + 2 * ring_x(m)) * (tile_y + 2 * m);
+}
+
+template <int S>
+__device__ __forceinline__ void ring_position(int tid, int tile_x, int tile_y, int &ltx, int &lty)
+{
+    constexpr int HX = (S + 1) / 2, HY = S;
+    if (tid < tile_x * tile_y) {
+        ltx = HX + tid % tile_x;
+        lty = HY + tid / tile_x;
+        return;
+    }
+    int m = 1;
+    while (m < S && tid >= ring_area<S>(m, tile_x, tile_y)) ++m;
+    int k = tid - ring_area<S>(m - 1, tile_x, tile_y);
+    const int wm = tile_x + 2 * ring_x(m), x0m = HX - ring_x(m), y0m = HY - m;
+    const int hm = tile_y + 2 * m;
+    const int wp = tile_x + 2 * ring_x(m - 1), x0p = HX - ring_x(m - 1), y0p = HY - (m - 1);
+    const int hp = tile_y + 2 * (m - 1);
+    const int lw = x0p - x0m;  // 0 or 1
+    if (k < wm) {
+        ltx = x0m + k;
+        lty = y0m;
+    } else if ((k -= wm) < wm) {
+        ltx = x0m + k;
+        lty = y0m + hm - 1;
+    } else if ((k -= wm) < hp * lw) {
+        ltx = x0m;
+        lty = y0p + k;
+    } else {
+        k -= hp * lw;
+        ltx = x0p + wp;
+        lty = y0p + k;
+    }
+}
 
 template <typename T, int S, bool FIRST, int TX, int TY, int PH>
 __device__ __forceinline__ void pipeline_step(Pipe<T, S> &st, const Geo &g, T *lds,
@@ -103,6 +154,7 @@ __device__ __forceinline__ void pipeline_step(Pipe<T, S> &st, const Geo &g, T *l
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         if (p < 2 * j + 2) continue;  // pipeline not yet filled for stage j
+        if (g.wave >= g.need[S - 1 - j]) continue;  // no column of this wave is needed
         const int c = j & 1;
         // level-j neighbours: z -/+ 1 from registers, in-plane from LDS
         const Vals<T> &up = (j == 0) ? st.B[s0] : st.F[j > 0 ? j - 1 : 0][s0];
@@ -188,8 +240,11 @@ stream3d_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t stride, i
     g.NT = BX * BY;
     const int tid = threadIdx.x;
     g.live = tid < g.NT;
-    const int ltx = g.live ? tid % BX : 0;
-    const int lty = g.live ? tid / BX : 0;
+    g.wave = tid & ~63;
+#pragma unroll
+    for (int m = 0; m < S; ++m) g.need[m] = ring_area<S>(m, tile_x, tile_y);
+    int ltx = 0, lty = 0;
+    if (g.live) ring_position<S>(tid, tile_x, tile_y, ltx, lty);
 
     // work item: XCD-aware (consecutive items run on the same XCD)
     const int G = gridDim.x;

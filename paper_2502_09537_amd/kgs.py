@@ -65,7 +65,8 @@ class KgsInfo(ctypes.Structure):
 
 class KgsServerConfig(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_int64), ("max_active", ctypes.c_int32),
-                ("steps_per_round", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("steps_per_round", ctypes.c_int32), ("round_work", ctypes.c_int64),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class KgsRequestInfo(ctypes.Structure):
@@ -419,8 +420,9 @@ class Server:
     results are numpy arrays on the host."""
 
     def __init__(self, budget_bytes: int, max_active: int = 0, steps_per_round: int = 50,
-                 stream=None):
-        cfg = KgsServerConfig(int(budget_bytes), int(max_active), int(steps_per_round))
+                 round_work: int = 0, stream=None):
+        cfg = KgsServerConfig(int(budget_bytes), int(max_active), int(steps_per_round),
+                              int(round_work))
         if stream is None:
             try:
                 stream = int(_torch().cuda.current_stream().cuda_stream)

@@ -112,9 +112,9 @@ def test_step_each_uneven_counts():
 
 
 def test_members_stepped_alone_in_between():
-    # a 3-D float64 member (n >= 64) steps alone with the ping-pong streaming
+    # a 3-D float64 member (n >= 96) steps alone with the ping-pong streaming
     # kernel between batched runs: the batch follows its current buffer
-    probs = [workloads.random_problem(3, 64, seed=5, tau=0.03, amp=0.5),
+    probs = [workloads.random_problem(3, 96, seed=5, tau=0.03, amp=0.5),
              workloads.random_problem(2, 40, seed=6, tau=0.03, amp=0.5)]
     say("alone + batched")
     sims = [kgs.simulation_from_problem(p) for p in probs]

@@ -65,18 +65,17 @@ def test_results_in_the_mix_equal_results_alone():
 def test_admission_respects_the_budget():
     probs = [workloads.gaussian_problem(2, 128, i, -6.0, 6.0, 0.01, 12) for i in range(6)]
     say("budget")
-    # admission needs the state plus the transient staging copy; this budget
-    # admits two requests but never a third
-    state = kgs.required_bytes(kgs.config_of(probs[0]))
-    staging = 4 * 128 * 128 * 8
-    srv = kgs.Server(budget_bytes=int(2.5 * state) + staging, steps_per_round=5)
+    # a request holds its state and its gathered result (32 bytes a point);
+    # this budget admits two requests but never a third
+    one = kgs.required_bytes(kgs.config_of(probs[0])) + 4 * 128 * 128 * 8
+    srv = kgs.Server(budget_bytes=int(2.5 * one), steps_per_round=5)
     ids = [srv.submit_problem(p) for p in probs]
     peak = 0
     while True:
         nr, nq = srv.run(1)
         st = srv.stats()
         peak = max(peak, st.device_bytes_used)
-        assert st.device_bytes_used <= 2 * state
+        assert st.device_bytes_used <= 2 * one
         assert nr <= 2
         if nr == 0 and nq == 0:
             break
@@ -90,20 +89,25 @@ def test_admission_respects_the_budget():
 def test_oversized_request_fails_and_cancel_works():
     say("oversized + cancel")
     big = workloads.gaussian_problem(3, 64, 1, -6.0, 6.0, 0.01, 5)
-    small = [workloads.gaussian_problem(1, 256, i, -6.0, 6.0, 0.01, 50) for i in range(3)]
-    srv = kgs.Server(budget_bytes=1 << 20, steps_per_round=10, max_active=1)
+    # 2-D n = 130 does not fit one workgroup: it advances in rounds
+    small = [workloads.gaussian_problem(2, 130, i, -6.0, 6.0, 0.01, 50) for i in range(3)]
+    srv = kgs.Server(budget_bytes=3 << 20, steps_per_round=10, max_active=1)
     rb = srv.submit_problem(big)
     rs = [srv.submit_problem(p) for p in small]
     srv.run(1)
     assert srv.poll(rb).state == kgs.KGS_REQ_FAILED
     assert srv.poll(rb).status == kgs.KGS_ENOMEM
     assert srv.poll(rs[0]).state == kgs.KGS_REQ_RUNNING
+    assert srv.poll(rs[0]).steps_done == 10
     srv.cancel(rs[2])  # queued
     assert srv.poll(rs[2]).state == kgs.KGS_REQ_CANCELLED
     srv.cancel(rs[0])  # running
     assert srv.poll(rs[0]).state == kgs.KGS_REQ_CANCELLED
+    with pytest.raises(kgs.KgsError):
+        srv.cancel(rs[0])
     while srv.run(1) != (0, 0):
         pass
+    assert srv.poll(rs[0]).state == kgs.KGS_REQ_CANCELLED
     assert srv.poll(rs[1]).state == kgs.KGS_REQ_DONE
     assert equal(srv.result(rs[1]), alone(small[1], 50)[0])
     srv.release(rs[1])
@@ -112,4 +116,46 @@ def test_oversized_request_fails_and_cancel_works():
     with pytest.raises(kgs.KgsError):
         srv.submit(kgs.make_config(2, 7, -1.0, 1.0, 0.01), np.zeros((7, 7)), np.zeros((7, 7)),
                    np.zeros((7, 7)), 3)
+    srv.close()
+
+
+def test_small_requests_finish_while_a_big_one_runs():
+    say("lanes")
+    big = workloads.gaussian_problem(3, 96, 3, -6.0, 6.0, 0.01, 2000)
+    small = [workloads.gaussian_problem(1, 512, 20 + i, -6.0, 6.0, 0.01, 300) for i in range(4)]
+    srv = kgs.Server(budget_bytes=8 << 30, steps_per_round=20)
+    rb = srv.submit_problem(big)
+    srv.run(1)
+    ids = [srv.submit_problem(p) for p in small]
+    rounds = 0
+    while any(srv.poll(i).state != kgs.KGS_REQ_DONE for i in ids):
+        srv.run(1)
+        rounds += 1
+        assert rounds < 90
+    # the small ones finished on their own lane while the big one still runs
+    assert srv.poll(rb).state == kgs.KGS_REQ_RUNNING
+    while srv.run(1) != (0, 0):
+        pass
+    assert srv.poll(rb).state == kgs.KGS_REQ_DONE
+    for rid, p in zip(ids + [rb], small + [big]):
+        ref, e_ref = alone(p, p.steps)
+        assert equal(srv.result(rid), ref)
+        assert srv.poll(rid).energy_end == e_ref
+    srv.close()
+
+
+def test_shortest_remaining_work_runs_first():
+    say("srpt")
+    # three 2-D requests of one size, very different step counts, admitted
+    # together; a round holds one request's steps
+    probs = [workloads.gaussian_problem(2, 256, 40 + i, -6.0, 6.0, 0.01, k)
+             for i, k in enumerate((300, 20, 100))]
+    srv = kgs.Server(budget_bytes=8 << 30, steps_per_round=10, round_work=256 * 256 * 10)
+    ids = [srv.submit_problem(p) for p in probs]
+    while srv.run(1) != (0, 0):
+        pass
+    t = [srv.poll(i).t_done for i in ids]
+    assert t[1] < t[2] < t[0]
+    for rid, p in zip(ids, probs):
+        assert equal(srv.result(rid), alone(p, p.steps)[0])
     srv.close()
