@@ -101,6 +101,31 @@ def cpu_baseline(problem, steps):
                       f"of the full grid, float64, {dt:.1f} s"}
 
 
+def rel_errors(got, ref):
+    """Max-norm relative errors (psi, u, v) of a state against a reference
+    state (numpy arrays or torch tensors); v is scaled by max(|v|, |u|)."""
+    def mx(a):
+        return float(abs(a).max())
+    (gp, gu, gv), (rp, ru, rv) = got, ref
+    return {"psi": mx(gp - rp) / max(mx(rp), 1e-300), "u": mx(gu - ru) / max(mx(ru), 1e-300),
+            "v": mx(gv - rv) / max(mx(rv), mx(ru), 1e-300)}
+
+
+def fp32_vs_fp64(kgs, problems, states, steps):
+    """Errors of float32-state results against the float64 path on the same
+    problems (the float64 path matches the float64 oracle to 1e-12)."""
+    worst = {"psi": 0.0, "u": 0.0, "v": 0.0}
+    for p, got in zip(problems, states):
+        p64 = p.with_(precision=0)
+        sim = kgs.simulation_from_problem(p64)
+        sim.step(steps)
+        ref = sim.read_state(as_torch=type(got[1]).__module__.startswith("torch"))
+        sim.close()
+        e = rel_errors(got, ref)
+        worst = {k: max(worst[k], e[k]) for k in worst}
+    return worst
+
+
 def _timed_ms(torch, stream, fn):
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -172,6 +197,10 @@ def bench_batched(args):
            "modes": results, "bitwise_identical_across_modes": identical,
            "speedup_vs_per_instance": results[best]["updates_per_s"] /
            results["per_instance"]["updates_per_s"]}
+    if prec == workloads.FP32:
+        sample = [probs[i] for i in (0, 17, 63)]
+        out["fp32_max_rel_err_vs_fp64"] = fp32_vs_fp64(kgs, sample, finals["batched"], steps)
+        out["fp32_error_sample"] = "instances 0, 17, 63 after the run, against float64 runs"
     print(json.dumps(out), flush=True)
 
 
@@ -243,6 +272,7 @@ def bench_serving(args):
             # results in the mix equal results alone (a sample of small requests)
             small = [(rid, j) for rid, j in ids if reqs[j].problem.points <= 1 << 16][:6]
             ok = True
+            fp32_err = {"psi": 0.0, "u": 0.0, "v": 0.0}
             for rid, j in small:
                 p = reqs[j].problem
                 got = srv.result(rid)
@@ -252,7 +282,15 @@ def bench_serving(args):
                 ref = sim.read_state()
                 sim.close()
                 ok &= all(np.array_equal(a, b) for a, b in zip(got, ref))
+                if p.precision == workloads.FP32:
+                    p64 = p.with_(precision=workloads.FP64)
+                    s64 = kgs.Simulation(kgs.config_of(p64), torch.complex(f[0], f[1]), f[2], f[3])
+                    s64.step(p.steps)
+                    e = rel_errors(got, s64.read_state())
+                    s64.close()
+                    fp32_err = {k: max(fp32_err[k], e[k]) for k in fp32_err}
             out["mix_equals_alone_bitwise"] = {"checked": len(small), "identical": bool(ok)}
+            out["fp32_max_rel_err_vs_fp64"] = fp32_err
         srv.close()
     best = out["continuous"]
     out["value"] = best["solves_per_s"]
@@ -410,6 +448,15 @@ def main():
         "energy_rel_drift": abs(e1 - e0) / abs(e0),
         "kernel_ms": kernel_ms,
     }
+    if args.precision == "fp32":
+        # the float32 state's error after the timed number of steps, against
+        # the float64 path from the same initial data
+        s32 = kgs.simulation_from_problem(p)
+        s32.step(args.steps)
+        got = s32.read_state(as_torch=True)
+        s32.close()
+        out["fp32_max_rel_err_vs_fp64"] = fp32_vs_fp64(kgs, [p], [got], args.steps)
+        del got
     if args.calibrate_copy:
         a = torch.empty(args.calibrate_copy << 17, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)

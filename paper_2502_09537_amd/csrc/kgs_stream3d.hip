@@ -36,6 +36,20 @@ struct Vals {
     T f[4];  // P, Q, U, V
 };
 
+// Element at a uniform plane pointer plus a per-thread 32-bit byte offset
+// (the scalar-base + vector-offset addressing of global memory).
+template <typename T>
+__device__ __forceinline__ T *at(T *base, uint32_t byte_offset)
+{
+    return reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_offset);
+}
+
+template <typename T>
+__device__ __forceinline__ const T *at(const T *base, uint32_t byte_offset)
+{
+    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_offset);
+}
+
 __device__ __forceinline__ int wrap(int v, int m)
 {
     v %= m;
@@ -43,11 +57,13 @@ __device__ __forceinline__ int wrap(int v, int m)
 }
 
 // Largest workgroup per instantiation: the four-sweep pipeline keeps 16
-// planes of FIFO per thread and needs more than 128 VGPRs.
-template <typename T, int S>
+// planes of FIFO per thread and needs more than 128 VGPRs, so at most 3
+// waves per SIMD (12 per workgroup); a compiled-in tile has exactly its
+// block of threads.
+template <typename T, int S, int TX = 0, int TY = 0>
 constexpr int max_threads()
 {
-    return S == 4 ? 512 : 1024;
+    return TX ? ((TX + 2 * ((S + 1) / 2)) * (TY + 2 * S) + 63) / 64 * 64 : S == 4 ? 768 : 1024;
 }
 
 // Per-thread pipeline registers.  Plane FIFOs are rings indexed by the
@@ -70,7 +86,7 @@ struct Geo {
     int need[5];         // stage j runs on threads below need[S - 1 - j]
     bool live, in_tile;  // has a column / writes its column
     int y;               // wrapped row of the column
-    int64_t col;         // offset of the column inside a plane
+    uint32_t colb;       // byte offset of the column inside a plane (< 2^31)
     int i_self, i_ym, i_yp;
     int i_xm0, i_xm1, i_xp0, i_xp1;  // x-neighbour slots for x-offset o = 0, 1
 };
@@ -138,12 +154,11 @@ __device__ __forceinline__ void pipeline_step(Pipe<T, S> &st, const Geo &g, T *l
     st.B[s0] = st.Bn;
     if (g.live && p + 1 < steps) {
         const int zn = z_load + 1 == n ? 0 : z_load + 1;
-        const T *pr_ = in + static_cast<int64_t>(zn) * plane_elems + g.col;
-        const T *pb_ = pr_ + 4 * stride;
+        const T *zb = in + static_cast<int64_t>(zn) * plane_elems;  // uniform
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            st.R[s2].f[q] = pr_[q * stride];
-            st.Bn.f[q] = pb_[q * stride];
+            st.R[s2].f[q] = *at(zb + q * stride, g.colb);
+            st.Bn.f[q] = *at(zb + (4 + q) * stride, g.colb);
         }
     }
     // x-offset of the updated colour in this row: the same for every stage
@@ -195,12 +210,11 @@ __device__ __forceinline__ void pipeline_step(Pipe<T, S> &st, const Geo &g, T *l
             // colour from stage S-2 one step ago
             const int z = wrap(z_load - S, n);  // n may be smaller than S
             const Vals<T> &oth = st.F[S - 2][s1];
-            T *oc = out + static_cast<int64_t>(4 * c) * stride + static_cast<int64_t>(z) * plane_elems + g.col;
-            T *oo = out + static_cast<int64_t>(4 * (c ^ 1)) * stride + static_cast<int64_t>(z) * plane_elems + g.col;
+            T *zo = out + static_cast<int64_t>(z) * plane_elems;  // uniform
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                oc[q * stride] = res.f[q];
-                oo[q * stride] = oth.f[q];
+                *at(zo + (4 * c + q) * stride, g.colb) = res.f[q];
+                *at(zo + (4 * (c ^ 1) + q) * stride, g.colb) = oth.f[q];
             }
         }
     }
@@ -222,7 +236,7 @@ __device__ __forceinline__ void pipeline_step(Pipe<T, S> &st, const Geo &g, T *l
 // TX, TY > 0: tile shape fixed at compile time (LDS offsets become
 // immediates); 0: taken from the arguments.
 template <typename T, int S, bool FIRST, int TX, int TY>
-__global__ void __launch_bounds__((max_threads<T, S>()))
+__global__ void __launch_bounds__((max_threads<T, S, TX, TY>()))
 stream3d_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t stride, int n,
                 int tiles_x, int tiles_y, int tile_x_arg, int tile_y_arg, int chunk_len, Coef k)
 {
@@ -275,7 +289,7 @@ stream3d_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t stride, i
     g.i_xp1 = lty * BX + min(ltx + 1, BX - 1);
 
     const int64_t plane_elems = static_cast<int64_t>(n) * H;
-    g.col = static_cast<int64_t>(g.y) * H + xh;
+    g.colb = static_cast<uint32_t>(g.y * H + xh) * static_cast<uint32_t>(sizeof(T));
 
     Pipe<T, S> st;
     {
@@ -292,12 +306,11 @@ stream3d_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t stride, i
     int z_load = wrap(z0 - S, n);  // plane loaded (consumed) at step p
     // the first plane: red into the slot of step 0, blue into Bn
     if (g.live) {
-        const T *pr_ = in + static_cast<int64_t>(z_load) * plane_elems + g.col;
-        const T *pb_ = pr_ + 4 * stride;
+        const T *zb = in + static_cast<int64_t>(z_load) * plane_elems;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            st.R[0].f[q] = pr_[q * stride];
-            st.Bn.f[q] = pb_[q * stride];
+            st.R[0].f[q] = *at(zb + q * stride, g.colb);
+            st.Bn.f[q] = *at(zb + (4 + q) * stride, g.colb);
         }
     }
     const int64_t pe = plane_elems;
@@ -328,8 +341,9 @@ hipError_t launch_typed(const Geometry &g, const StreamShape &sh, const T *in, T
     const size_t lds = static_cast<size_t>(2) * S * 3 * NT * sizeof(T);
     if (threads > max_threads<T, S>() || items > 0x7fffffff || lds > 160 * 1024)
         return hipErrorInvalidValue;
-    // the library's default shape for float64 four-sweep launches is
-    // compiled with its tile fixed
+    // float64 four-sweep launches of the library's default tile are
+    // compiled with the tile fixed (measured on MI355X: 16x16 beats taller
+    // tiles of up to 768 threads, e.g. 16x28, at 256^3)
     auto kern = first ? stream3d_kernel<T, S, true, 0, 0> : stream3d_kernel<T, S, false, 0, 0>;
     if constexpr (sizeof(T) == 8 && S == 4) {
         if (sh.tile_x == 16 && sh.tile_y == 16)
@@ -352,10 +366,12 @@ bool stream3d_shape_ok(const Geometry &g, const StreamShape &sh, int elem_bytes)
         return false;
     if (sh.steps != 1 && sh.steps != 2) return false;
     if (sh.tile_x < 1 || sh.tile_y < 1 || sh.chunk < 1) return false;
+    // per-thread offsets inside a plane are 32-bit byte offsets
+    if (static_cast<int64_t>(g.n) * (g.n / 2) * elem_bytes >= (int64_t(1) << 31)) return false;
     const int S = 2 * sh.steps;
     const int BX = sh.tile_x + 2 * ((S + 1) / 2), BY = sh.tile_y + 2 * S;
     const int NT = BX * BY;
-    const int limit = S == 4 ? 512 : 1024;
+    const int limit = S == 4 ? max_threads<float, 4>() : max_threads<float, 2>();
     if ((NT + 63) / 64 * 64 > limit) return false;
     return static_cast<size_t>(2) * S * 3 * NT * elem_bytes <= 160 * 1024;
 }

@@ -163,6 +163,23 @@ def test_energy_conserved_1d_config_10k_steps():
     assert worst <= 1e-12
 
 
+def test_energy_drift_float32_state_is_bounded():
+    # float32 storage rounds the state after every step: the energy is no
+    # longer conserved to round-off of float64, but stays at the level of
+    # float32 rounding (stated, with a loose bound)
+    p = workloads.config_1d().with_(precision=workloads.FP32)
+    say("energy drift 1d fp32 1e4 steps")
+    sim = kgs.simulation_from_problem(p)
+    e0 = sim.energy()
+    worst = 0.0
+    for _ in range(10):
+        sim.step(1000)
+        worst = max(worst, abs(sim.energy() - e0) / abs(e0))
+    sim.close()
+    print("  relative drift (float32 state)", worst, flush=True)
+    assert worst <= 1e-4
+
+
 def test_energy_is_deterministic():
     p = workloads.config_2d(n=256)
     say("energy determinism 2d 256")

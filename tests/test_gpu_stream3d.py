@@ -54,6 +54,8 @@ SHAPES = [
     (40, 2, 20, 12, 7, 1),
     (40, 3, 16, 16, 13, 2),   # the compiled-in float64 tile, ragged tiles and chunks
     (36, 4, 16, 16, 128, 2),  # chunk longer than the grid
+    (58, 3, 16, 28, 20, 2),   # 720 threads (3 waves per SIMD), ragged
+    (30, 2, 20, 20, 9, 2),    # a 768-thread runtime shape
 ]
 
 
