@@ -136,9 +136,12 @@ const char *kgs_status_string(int status);
 enum {
     KGS_KERNEL_AUTO = 0,   /* library's choice for the grid                    */
     KGS_KERNEL_SWEEP = 1,  /* one launch per colour sweep, one thread per point */
-    KGS_KERNEL_STREAM = 2, /* 3-D only: z-streaming kernel, 2 or 4 colour sweeps
-                              (1 or 2 full steps) per launch between two state
-                              buffers (the handle then holds twice the state) */
+    KGS_KERNEL_STREAM = 2, /* 2-D and 3-D: streaming kernels, 2 or 4 colour
+                              sweeps (1 or 2 full steps) per launch between
+                              two state buffers (the handle then holds twice
+                              the state); 3-D streams along axis 0 with
+                              tile_x x tile_y tiles, 2-D along axis 0 with
+                              one wave per 64-lane tile of axis 1          */
     KGS_KERNEL_RESIDENT = 3, /* small grids (at most 4096 points per colour and
                                 6 x points-per-colour x element bytes <= 160 KiB,
                                 e.g. 1-D n <= 6826 float64 / 8192 float32):
@@ -150,10 +153,11 @@ typedef struct {
     int32_t kernel;        /* KGS_KERNEL_*                                    */
     int32_t block;         /* KGS_KERNEL_SWEEP: threads per workgroup (64..1024,
                               multiple of 64); 0 = default                      */
-    int32_t tile_x;        /* KGS_KERNEL_STREAM: output tile width in points of
-                              one colour along the last axis                   */
-    int32_t tile_y;        /* KGS_KERNEL_STREAM: output tile height (axis 1)    */
-    int32_t chunk;         /* KGS_KERNEL_STREAM: planes of axis 0 per workgroup */
+    int32_t tile_x;        /* KGS_KERNEL_STREAM, 3-D: output tile width in points
+                              of one colour along the last axis (2-D: unused) */
+    int32_t tile_y;        /* KGS_KERNEL_STREAM, 3-D: output tile height (axis 1) */
+    int32_t chunk;         /* KGS_KERNEL_STREAM: planes (3-D) or rows (2-D) of
+                              axis 0 per workgroup (3-D) or wave (2-D)        */
     int32_t steps_per_launch; /* KGS_KERNEL_STREAM: 1 or 2 DP-AVF2 steps (2 or 4
                               colour sweeps) per launch                        */
     int32_t reserved[2];   /* must be 0                                       */

@@ -158,6 +158,10 @@ kgs::Geometry make_geometry(const kgs_config &c)
 //    power of two (8..128) that still gives about 200 workgroups (256^3:
 //    chunk 128, 9.9e10 updates/s vs 4.7e10 for one sweep per launch; 128^3:
 //    chunk 16, 9.1e10 vs 5.4e10; smaller n run faster with sweeps);
+//  * for 2-D float64 grids with n >= 512, the 2-D streaming kernel with two
+//    steps per launch and the longest row chunk (8..64) that gives about
+//    1024 waves (1024^2: 7.4e10 updates/s vs 4.2e10 for sweeps; smaller
+//    grids have too few tasks);
 //  * one sweep per launch otherwise (float32 3-D states run fastest that way
 //    at most sizes: 1.2e11 updates/s at 256^3).
 kgs_tuning default_tuning(const kgs_config &c)
@@ -173,6 +177,10 @@ kgs_tuning default_tuning(const kgs_config &c)
     const kgs::Geometry g = make_geometry(c);
     if (kgs::resident_fits(g.count, static_cast<int>(elem_bytes(c.precision)))) {
         t.kernel = KGS_KERNEL_RESIDENT;
+    } else if (c.dim == 2 && c.precision == KGS_FP64 && c.n >= 512) {
+        t.kernel = KGS_KERNEL_STREAM;
+        t.chunk = 64;
+        while (t.chunk > 8 && kgs::stream2d_tasks(c.n, t.chunk) < 1024) t.chunk /= 2;
     } else if (c.dim == 3 && c.precision == KGS_FP64 && c.n >= 96) {
         t.kernel = KGS_KERNEL_STREAM;
         const int64_t tiles = static_cast<int64_t>((c.n / 2 + 15) / 16) * ((c.n + 15) / 16);
@@ -393,6 +401,20 @@ int sim_create_pooled(const kgs_config *cfg, const double *P, const double *Q, c
 
 int default_kernel(const kgs_config &cfg) { return default_tuning(cfg).kernel; }
 
+int sim_ensure_state2(kgs_sim *s)
+{
+    if (s->state2) return KGS_OK;
+    int rc = check_device(s);
+    if (rc != KGS_OK) return rc;
+    hipError_t e = alloc_device(s, &s->state2, 8 * s->plane_bytes);
+    if (e != hipSuccess) {
+        s->state2 = nullptr;
+        return hip_fail(s, e, "device allocation (second state buffer)");
+    }
+    s->device_bytes += static_cast<int64_t>(8 * s->plane_bytes);
+    return KGS_OK;
+}
+
 void sim_destroy_pooled(kgs_sim *s)
 {
     if (!s) return;
@@ -496,8 +518,24 @@ int kgs_step(kgs_sim *s, int64_t nsteps)
         bool first = true;
         for (int64_t left = nsteps; left > 0 && rc == KGS_OK;) {
             const int st = (sh.steps == 2 && left >= 2) ? 2 : 1;
-            hipError_t e = kgs::launch_stream3d(s->geo, prec, sh, 2 * st, s->state, s->state2,
-                                                first, s->coef, s->stream);
+            hipError_t e;
+            if (s->cfg.dim == 2) {
+                kgs::Stream2dMember m;
+                std::memset(&m, 0, sizeof(m));
+                m.in = s->state;
+                m.out = s->state2;
+                m.stride = s->geo.stride;
+                m.k = s->coef;
+                m.n = s->geo.n;
+                m.chunk = sh.chunk;
+                m.tiles_x = kgs::stream2d_tiles_x(s->geo.n);
+                m.first = first ? 1 : 0;
+                e = kgs::launch_stream2d(prec, 2 * st, m, nullptr, 1,
+                                         kgs::stream2d_tasks(s->geo.n, sh.chunk), s->stream);
+            } else {
+                e = kgs::launch_stream3d(s->geo, prec, sh, 2 * st, s->state, s->state2, first,
+                                         s->coef, s->stream);
+            }
             if (e != hipSuccess) return hip_fail(s, e, "stream kernel launch");
             std::swap(s->state, s->state2);
             first = false;
@@ -624,20 +662,18 @@ int kgs_set_tuning(kgs_sim *s, const kgs_tuning *t)
     if (nt.block < 64 || nt.block > 1024 || nt.block % 64)
         return fail(s, KGS_EINVAL, "block must be a multiple of 64 in [64, 1024]");
     if (nt.kernel == KGS_KERNEL_STREAM) {
-        if (s->cfg.dim != 3) return fail(s, KGS_EINVAL, "the streaming kernel is 3-D only");
-        kgs::StreamShape sh = {nt.tile_x, nt.tile_y, nt.chunk, nt.steps_per_launch};
-        if (!kgs::stream3d_shape_ok(s->geo, sh, static_cast<int>(elem_bytes(s->cfg.precision))))
-            return fail(s, KGS_EINVAL, "tile/chunk/steps do not fit the streaming kernel");
-        if (!s->state2) {
-            int rc = check_device(s);
-            if (rc != KGS_OK) return rc;
-            hipError_t e = alloc_device(s, &s->state2, 8 * s->plane_bytes);
-            if (e != hipSuccess) {
-                s->state2 = nullptr;
-                return hip_fail(s, e, "hipMalloc (second state buffer)");
-            }
-            s->device_bytes += static_cast<int64_t>(8 * s->plane_bytes);
+        if (s->cfg.dim == 1) return fail(s, KGS_EINVAL, "the streaming kernels are 2-D and 3-D");
+        if (s->cfg.dim == 2) {
+            if ((nt.steps_per_launch != 1 && nt.steps_per_launch != 2) || nt.chunk < 1 ||
+                kgs::stream2d_tasks(s->geo.n, nt.chunk) < 1)
+                return fail(s, KGS_EINVAL, "chunk/steps do not fit the 2-D streaming kernel");
+        } else {
+            kgs::StreamShape sh = {nt.tile_x, nt.tile_y, nt.chunk, nt.steps_per_launch};
+            if (!kgs::stream3d_shape_ok(s->geo, sh, static_cast<int>(elem_bytes(s->cfg.precision))))
+                return fail(s, KGS_EINVAL, "tile/chunk/steps do not fit the streaming kernel");
         }
+        const int rc = kgs::sim_ensure_state2(s);
+        if (rc != KGS_OK) return rc;
     } else if (nt.kernel == KGS_KERNEL_RESIDENT) {
         if (!kgs::resident_fits(s->geo.count, static_cast<int>(elem_bytes(s->cfg.precision))))
             return fail(s, KGS_EINVAL, "the grid does not fit the resident kernel");

@@ -4,7 +4,10 @@
 // optionally with the whole step loop captured in a hipGraph and replayed.
 // Members small enough for one workgroup form classes of their own that the
 // resident kernel advances through a whole run in a single launch (one
-// workgroup per member).
+// workgroup per member).  Uniform runs of 2-D classes use the 2-D streaming
+// kernel: two steps per launch over all members, between each member's two
+// state buffers, with an even number of launches so that every member ends
+// in its own buffer.
 #include <algorithm>
 #include <cstring>
 #include <map>
@@ -31,6 +34,12 @@ struct BatchClass {
     int64_t blocks = 0;     // sweep classes: workgroups per launch
     int64_t max_count = 0;  // resident classes: largest member
     int64_t step_off = 0;   // resident classes: first slot in kgs_batch::d_steps
+    // 2-D streaming (uniform runs of 2-D sweep classes): descriptors for the
+    // first launch, the even and the odd launches, 3 x members each
+    bool s2 = false;
+    kgs::Stream2dMember *d_s2 = nullptr, *h_s2 = nullptr;
+    int64_t s2_tasks = 0;
+    int s2_chunk = 0;
 };
 
 }  // namespace
@@ -82,6 +91,10 @@ void destroy(kgs_batch *b)
         }
         if (c.h_res && hipHostFree(c.h_res) != hipSuccess) {
         }
+        if (c.d_s2 && hipFree(c.d_s2) != hipSuccess) {
+        }
+        if (c.h_s2 && hipHostFree(c.h_s2) != hipSuccess) {
+        }
     }
     if (b->d_steps && hipFree(b->d_steps) != hipSuccess) {
     }
@@ -110,8 +123,11 @@ int refresh_descriptors(kgs_batch *b)
     };
     bool changed = false;
     for (auto &c : b->classes)
-        for (size_t i = 0; i < c.members.size(); ++i)
-            changed |= held(c, i) != b->sims[c.members[i]]->state;
+        for (size_t i = 0; i < c.members.size(); ++i) {
+            const kgs_sim *m = b->sims[c.members[i]];
+            changed |= held(c, i) != m->state;
+            if (c.s2) changed |= c.h_s2[i].out != m->state2;
+        }
     if (!changed && b->uploaded) return KGS_OK;
     hipError_t e = hipStreamSynchronize(b->own);
     if (e != hipSuccess) return bhip(b, e, "hipStreamSynchronize");
@@ -125,6 +141,21 @@ int refresh_descriptors(kgs_batch *b)
             for (size_t i = 0; i < nm; ++i) c.h_members[i].state = b->sims[c.members[i]]->state;
             e = hipMemcpyAsync(c.d_members, c.h_members, nm * sizeof(kgs::BatchMember),
                                hipMemcpyHostToDevice, b->own);
+            if (e == hipSuccess && c.s2) {
+                // [first launch | even launches | odd launches]
+                for (size_t i = 0; i < nm; ++i) {
+                    const kgs_sim *m = b->sims[c.members[i]];
+                    kgs::Stream2dMember &f = c.h_s2[i], &ev = c.h_s2[nm + i], &od = c.h_s2[2 * nm + i];
+                    f.in = ev.in = m->state;
+                    od.out = m->state;
+                    f.out = ev.out = m->state2;
+                    od.in = m->state2;
+                    f.first = 1;
+                    ev.first = od.first = 0;
+                }
+                e = hipMemcpyAsync(c.d_s2, c.h_s2, 3 * nm * sizeof(kgs::Stream2dMember),
+                                   hipMemcpyHostToDevice, b->own);
+            }
         }
         if (e != hipSuccess) return bhip(b, e, "hipMemcpyAsync (batch descriptors)");
     }
@@ -146,9 +177,33 @@ hipError_t enqueue_uniform(kgs_batch *b, int64_t nsteps)
                                             b->own);
         if (e != hipSuccess) return e;
     }
+    // 2-D streaming classes: launches of 2 steps, and of 1 step where needed
+    // to keep the number of launches even, then the closing red sweep
+    const bool streamed = nsteps >= 2;
+    for (auto &c : b->classes) {
+        if (!c.s2 || !streamed) continue;
+        // K = 2a + r steps: a launches of 4 sweeps and r of 2, one 4 split
+        // into two 2s when that count is odd
+        const int64_t a = nsteps / 2, r = nsteps % 2;
+        const int64_t split = (a + r) % 2;
+        std::vector<int> stages(static_cast<size_t>(a - split), 4);
+        for (int64_t i = 0; i < 2 * split + r; ++i) stages.push_back(2);
+        const int nm = static_cast<int>(c.members.size());
+        kgs::Stream2dMember none;
+        std::memset(&none, 0, sizeof(none));
+        for (size_t i = 0; i < stages.size(); ++i) {
+            const kgs::Stream2dMember *list = c.d_s2 + (i == 0 ? 0 : (i % 2 ? 2 * nm : nm));
+            hipError_t e = kgs::launch_stream2d(c.precision, stages[i], none, list, nm, c.s2_tasks,
+                                                b->own);
+            if (e != hipSuccess) return e;
+        }
+        hipError_t e = kgs::launch_batch_sweep(c.dim, c.precision, c.d_members, nm, c.blocks,
+                                               nullptr, 0, kgs::PASS_R_ADJ, b->own);
+        if (e != hipSuccess) return e;
+    }
     auto sweep = [&](int kind) {
         for (auto &c : b->classes) {
-            if (c.resident) continue;
+            if (c.resident || (c.s2 && streamed)) continue;
             hipError_t e = kgs::launch_batch_sweep(c.dim, c.precision, c.d_members,
                                                    static_cast<int>(c.members.size()), c.blocks,
                                                    nullptr, 0, kind, b->own);
@@ -313,6 +368,51 @@ int kgs_batch_create(kgs_sim *const *sims, int32_t count, void *stream, kgs_batc
                 break;
             }
             c.blocks = blocks;
+            if (c.dim == 2) {
+                // 2-D streaming for uniform runs: every member needs its
+                // second buffer; the row chunk gives >= 2048 tasks (waves)
+                // where the members allow it
+                c.s2 = true;
+                const size_t nm = c.members.size();
+                for (size_t i = 0; i < nm && code == KGS_OK; ++i)
+                    code = kgs::sim_ensure_state2(b->sims[c.members[i]]);
+                if (code != KGS_OK) {
+                    b->err = "second state buffer for the 2-D streaming kernel";
+                    break;
+                }
+                int chunk = 64;
+                auto tasks = [&](int ch) {
+                    int64_t t = 0;
+                    for (size_t i = 0; i < nm; ++i) t += kgs::stream2d_tasks(b->sims[c.members[i]]->geo.n, ch);
+                    return t;
+                };
+                while (chunk > 8 && tasks(chunk) < 2048) chunk /= 2;
+                c.s2_chunk = chunk;
+                const size_t s2bytes = 3 * nm * sizeof(kgs::Stream2dMember);
+                if ((e = hipMalloc(reinterpret_cast<void **>(&c.d_s2), s2bytes)) != hipSuccess ||
+                    (e = hipHostMalloc(reinterpret_cast<void **>(&c.h_s2), s2bytes,
+                                       hipHostMallocDefault)) != hipSuccess) {
+                    code = bhip(b, e, "descriptor allocation (2-D streaming)");
+                    break;
+                }
+                int64_t tb = 0;
+                for (size_t i = 0; i < nm; ++i) {
+                    const kgs_sim *x = b->sims[c.members[i]];
+                    for (int v = 0; v < 3; ++v) {
+                        kgs::Stream2dMember &m = c.h_s2[v * nm + i];
+                        std::memset(&m, 0, sizeof(m));
+                        m.stride = x->geo.stride;
+                        m.task_begin = tb;
+                        m.k = x->coef;
+                        m.n = x->geo.n;
+                        m.chunk = chunk;
+                        m.tiles_x = kgs::stream2d_tiles_x(x->geo.n);
+                        // in/out/first are set by refresh_descriptors
+                    }
+                    tb += kgs::stream2d_tasks(x->geo.n, chunk);
+                }
+                c.s2_tasks = tb;
+            }
         }
         if (code == KGS_OK && step_slots > 0) {
             const size_t bytes = static_cast<size_t>(step_slots) * sizeof(int64_t);

@@ -105,6 +105,22 @@ struct ResidentMember {
     int count;  // points per colour
 };
 
+// One member of a 2-D streaming launch (kgs_stream2d.hip): S sweeps from
+// `in` to `out` (distinct buffers), tasks (one wave each) [task_begin,
+// task_begin + tiles_x * ceil(n / chunk)) of the launch; `first` makes the
+// first sweep R_BASE instead of R_ADJ_BASE.
+struct Stream2dMember {
+    const void *in;
+    void *out;
+    int64_t stride;
+    int64_t task_begin;
+    Coef k;
+    int n;
+    int chunk;
+    int tiles_x;
+    int first;
+};
+
 // Upper bound on the LDS one resident workgroup may use (the device limit
 // can lower it).
 constexpr int kResidentMaxLds = 160 * 1024;
@@ -143,6 +159,14 @@ hipError_t resident_prepare();
 hipError_t launch_resident(int dim, int precision, const ResidentMember &one,
                            const ResidentMember *list, const int64_t *steps_each,
                            int64_t steps_all, int nm, int64_t max_count, hipStream_t s);
+// 2-D streaming kernel: tiles along x and tasks of one member (the same for
+// 2 and 4 sweeps per launch); a launch of `stages` (2 or 4) sweeps over one
+// member (list == NULL, nm == 1) or over the nm members of `list` (device
+// memory, sorted by task_begin, all of one precision).
+int stream2d_tiles_x(int n);
+int64_t stream2d_tasks(int n, int chunk);
+hipError_t launch_stream2d(int precision, int stages, const Stream2dMember &one,
+                           const Stream2dMember *list, int nm, int64_t total_tasks, hipStream_t s);
 // Writes the double-double sum of the energy density (without h^dim) to
 // out[0] + out[1] (device memory); `partials` holds 2*energy_partial_slots()
 // doubles.

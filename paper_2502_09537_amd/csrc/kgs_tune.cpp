@@ -32,6 +32,19 @@ std::vector<kgs_tuning> candidates(const kgs_sim *s)
         out.push_back(t);
     };
     for (int b : {128, 256, 512}) sweep(b);
+    if (s->cfg.dim == 2) {
+        for (int chunk : {8, 16, 32, 64, 128})
+            for (int spl : {1, 2}) {
+                if (kgs::stream2d_tasks(s->geo.n, chunk) < 1) continue;
+                kgs_tuning t;
+                std::memset(&t, 0, sizeof(t));
+                t.kernel = KGS_KERNEL_STREAM;
+                t.block = 256;
+                t.chunk = chunk;
+                t.steps_per_launch = spl;
+                out.push_back(t);
+            }
+    }
     if (s->cfg.dim == 3) {
         const int eb = s->cfg.precision == KGS_FP32 ? 4 : 8;
         const int shapes[][4] = {

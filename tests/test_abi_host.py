@@ -107,6 +107,9 @@ def test_required_bytes(L):
     assert 2 * state <= kgs.required_bytes(cfg) < 2 * state + (1 << 20)
     cfg32 = good(dim=3, n=256, precision=kgs.KGS_FP32)
     assert state // 2 <= kgs.required_bytes(cfg32) < state // 2 + (1 << 20)
+    # 2-D float64 grids of n >= 512 stream too (two states); float32 sweeps (one)
     cfg2 = good(dim=2, n=1024)
     state2 = 8 * (1024 ** 2 // 2) * 8
-    assert state2 <= kgs.required_bytes(cfg2) < state2 + (1 << 20)
+    assert 2 * state2 <= kgs.required_bytes(cfg2) < 2 * state2 + (1 << 20)
+    cfg2f = good(dim=2, n=1024, precision=kgs.KGS_FP32)
+    assert state2 // 2 <= kgs.required_bytes(cfg2f) < state2 // 2 + (1 << 20)

@@ -150,3 +150,58 @@ def test_batch_rejects_bad_input():
         b.step_each([-2])
     b.close()
     s.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+@pytest.mark.parametrize("prec", [workloads.FP64, workloads.FP32])
+def test_2d_batches_stream_and_equal_individual_runs(graph, prec):
+    # uneven 2-D members beyond one workgroup: uniform runs use the 2-D
+    # streaming kernel (2 steps per launch, an even number of launches)
+    sizes = [130, 200, 256, 1030, 66 * 2, 90 * 2]
+    probs = [workloads.random_problem(2, n, seed=500 + n, tau=0.02, amp=0.5, precision=prec)
+             for n in sizes]
+    say("2-D batch streaming, graph =", graph, "prec", prec)
+    for k_run in ([1, 2, 3], [7, 7]):
+        ref = []
+        for p in probs:
+            t = kgs.KgsTuning()
+            t.kernel = kgs.KGS_KERNEL_SWEEP
+            t.block = 256
+            s = kgs.simulation_from_problem(p, tuning=t)
+            s.step(sum(k_run))
+            ref.append(s.read_state())
+            s.close()
+        sims = [kgs.simulation_from_problem(p) for p in probs]
+        b = kgs.Batch(sims, graph=graph)
+        for k in k_run:
+            b.step(k)
+            sims[0].energy()  # eager work between (replayed) runs
+        got = states(sims)
+        b.close()
+        for s in sims:
+            s.close()
+        assert same(got, ref), k_run
+
+
+def test_2d_members_stepped_alone_between_streamed_batch_runs():
+    probs = [workloads.random_problem(2, 512, seed=61, tau=0.02, amp=0.5),
+             workloads.random_problem(2, 150, seed=62, tau=0.02, amp=0.5)]
+    say("2-D alone + batched")
+    sims = [kgs.simulation_from_problem(p) for p in probs]
+    assert sims[0].tuning.kernel == kgs.KGS_KERNEL_STREAM  # swaps its buffers
+    b = kgs.Batch(sims)
+    b.step(4)
+    sims[0].step(3)
+    sims[1].step(3)
+    b.step(5)
+    got = states(sims)
+    b.close()
+    for s in sims:
+        s.close()
+    ref = []
+    for p in probs:
+        s = kgs.simulation_from_problem(p)
+        s.step(12)
+        ref.append(s.read_state())
+        s.close()
+    assert same(got, ref)

@@ -91,8 +91,9 @@ def test_stream_rejects_bad_shapes():
         with pytest.raises(kgs.KgsError):
             sim.tuning = bad
     sim.close()
-    p2 = workloads.random_problem(2, 8, seed=1)
-    sim = kgs.simulation_from_problem(p2)
+    # 1-D grids have no streaming kernel
+    p1 = workloads.random_problem(1, 8, seed=1)
+    sim = kgs.simulation_from_problem(p1)
     with pytest.raises(kgs.KgsError):
         sim.tuning = tuning(4, 4, 4, 1)
     sim.close()
