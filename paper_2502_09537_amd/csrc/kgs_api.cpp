@@ -401,6 +401,11 @@ int sim_create_pooled(const kgs_config *cfg, const double *P, const double *Q, c
 
 int default_kernel(const kgs_config &cfg) { return default_tuning(cfg).kernel; }
 
+int64_t state_bytes(const kgs_config &cfg)
+{
+    return 8 * make_geometry(cfg).stride * static_cast<int64_t>(elem_bytes(cfg.precision));
+}
+
 int sim_ensure_state2(kgs_sim *s)
 {
     if (s->state2) return KGS_OK;

@@ -11,10 +11,12 @@
 //   * big lane: every other grid, in rounds.  A round advances the running
 //     requests with the least remaining work (points x steps left) first, up
 //     to round_work point-steps per round and steps_per_round steps per
-//     request: 3-D float64 grids with their own z-streaming kernel, the rest
-//     in one batched launch sequence per (dimension, precision) with
-//     per-request step counts.  Shortest-remaining-work-first keeps the mean
-//     and median latency low when the device is oversubscribed.
+//     request: 3-D float64 grids with their own z-streaming kernel, 2-D
+//     grids together in 2-D streaming launches (one task list over all of
+//     them), the rest in one batched launch sequence per (dimension,
+//     precision) with per-request step counts.  Shortest-remaining-work-
+//     first keeps the mean and median latency low when the device is
+//     oversubscribed.
 // The host does not wait for the GPU in steady state: device memory comes
 // from a private pool in stream order, energies land in pinned slots, a
 // finished request's state is gathered on the device and copied to the host
@@ -45,7 +47,7 @@ namespace {
 
 constexpr int64_t kDefaultRoundWork = int64_t(1) << 31;  // point-steps per big-lane round
 constexpr size_t kMaxAhead = 2;                          // rounds queued ahead, per lane
-constexpr int kRingSlots = 4;                            // staging slots per lane
+constexpr int kRingSlots = 16;                           // staging slots per lane
 constexpr int kSlotChunk = 1024;                         // energy slots per allocation
 
 double now_s()
@@ -63,7 +65,7 @@ struct Request {
     int64_t done_steps = 0;  // steps enqueued on the device
     int32_t state = KGS_REQ_QUEUED;
     int32_t status = KGS_OK;
-    int64_t bytes = 0;   // device bytes while running: state + gathered result
+    int64_t bytes = 0;   // device bytes while running: state(s) + gathered result
     int64_t points = 0;
     double t_submit = 0, t_admit = 0, t_done = 0;
     double e0 = 0, e1 = 0;
@@ -534,6 +536,79 @@ int run_small(kgs_server *s)
 
 // ---- big lane -----------------------------------------------------------
 
+// 2-D requests of one precision taking k >= 2 steps this round: launches of
+// 2 steps (and of 1 step where needed to keep their number even, so that
+// every request ends in its own buffer) of the 2-D streaming kernel over
+// all of them, then the closing red sweep as one batched sweep.
+int run_stream2d(kgs_server *s, int prec, int64_t k, const std::vector<Request *> &rs)
+{
+    const int nm = static_cast<int>(rs.size());
+    int chunk = 64;
+    auto tasks = [&](int ch) {
+        int64_t t = 0;
+        for (const Request *r : rs) t += kgs::stream2d_tasks(r->sim->geo.n, ch);
+        return t;
+    };
+    while (chunk > 8 && tasks(chunk) < 2048) chunk /= 2;
+    const size_t s2_bytes = align_up(3 * nm * sizeof(kgs::Stream2dMember), 256);
+    const size_t bm_bytes = align_up(nm * sizeof(kgs::BatchMember), 256);
+    int rc = KGS_OK;
+    Ring::Slot *sl = ring_take(s, LANE_BIG, s2_bytes + bm_bytes, rc);
+    if (!sl) return rc;
+    auto *d = reinterpret_cast<kgs::Stream2dMember *>(sl->h);
+    auto *bm = reinterpret_cast<kgs::BatchMember *>(sl->h + s2_bytes);
+    const int bb = kgs::batch_block();
+    int64_t tb = 0, blocks = 0;
+    for (int i = 0; i < nm; ++i) {
+        const kgs_sim *x = rs[i]->sim;
+        for (int v = 0; v < 3; ++v) {  // [first launch | even | odd]
+            kgs::Stream2dMember &m = d[v * nm + i];
+            std::memset(&m, 0, sizeof(m));
+            m.in = v == 2 ? x->state2 : x->state;
+            m.out = v == 2 ? x->state : x->state2;
+            m.stride = x->geo.stride;
+            m.task_begin = tb;
+            m.k = x->coef;
+            m.n = x->geo.n;
+            m.chunk = chunk;
+            m.tiles_x = kgs::stream2d_tiles_x(x->geo.n);
+            m.first = v == 0 ? 1 : 0;
+        }
+        tb += kgs::stream2d_tasks(x->geo.n, chunk);
+        std::memset(&bm[i], 0, sizeof(bm[i]));
+        bm[i].state = x->state;
+        bm[i].stride = x->geo.stride;
+        bm[i].count = x->geo.count;
+        bm[i].block_begin = blocks;
+        bm[i].k = x->coef;
+        bm[i].n = x->geo.n;
+        blocks += (x->geo.count + bb - 1) / bb;
+    }
+    hipStream_t st = s->lane[LANE_BIG];
+    hipError_t e = hipMemcpyAsync(sl->d, sl->h, s2_bytes + bm_bytes, hipMemcpyHostToDevice, st);
+    const int64_t a = k / 2, r = k % 2, split = (a + r) % 2;
+    std::vector<int> stages(static_cast<size_t>(a - split), 4);
+    for (int64_t i = 0; i < 2 * split + r; ++i) stages.push_back(2);
+    const auto *dd = reinterpret_cast<const kgs::Stream2dMember *>(sl->d);
+    kgs::Stream2dMember none;
+    std::memset(&none, 0, sizeof(none));
+    for (size_t i = 0; i < stages.size() && e == hipSuccess; ++i)
+        e = kgs::launch_stream2d(prec, stages[i], none, dd + (i == 0 ? 0 : (i % 2 ? 2 * nm : nm)), nm,
+                                 tb, st);
+    if (e == hipSuccess && blocks > 0x7fffffff) e = hipErrorInvalidValue;
+    if (e == hipSuccess)
+        e = kgs::launch_batch_sweep(2, prec, reinterpret_cast<const kgs::BatchMember *>(sl->d + s2_bytes),
+                                    nm, blocks, nullptr, 0, kgs::PASS_R_ADJ, st);
+    const hipError_t e2 = ring_done(s, LANE_BIG, sl);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess)
+        for (Request *q : rs) {
+            q->status = status_of(e);
+            q->err = std::string("2-D streaming launch: ") + hipGetErrorName(e);
+        }
+    return KGS_OK;
+}
+
 // One round: the requests with the least remaining work first, up to the
 // round's work quantum (at least one request).
 int run_big(kgs_server *s)
@@ -556,12 +631,21 @@ int run_big(kgs_server *s)
         work += r->points * k;
     }
     hipStream_t st = s->lane[LANE_BIG];
-    // own-kernel grids now; sweep-kernel grids batched by (dim, precision)
+    // 3-D own-kernel grids now; 2-D grids taking >= 2 steps streamed
+    // together by (precision, steps); the rest batched by (dim, precision)
     std::map<int, std::vector<std::pair<Request *, int64_t>>> cls;
+    std::map<std::pair<int, int64_t>, std::vector<Request *>> s2;
     for (auto &pk : pick) {
         Request *r = pk.first;
         if (pk.second == 0) continue;
-        if (r->sim->tuning.kernel == KGS_KERNEL_STREAM) {
+        if (r->cfg.dim == 2 && pk.second >= 2) {
+            if (kgs::sim_ensure_state2(r->sim) == KGS_OK) {
+                s2[{r->cfg.precision, pk.second}].push_back(r);
+                continue;
+            }
+            r->sim->err.clear();  // no second buffer: sweeps instead
+        }
+        if (r->cfg.dim == 3 && r->sim->tuning.kernel == KGS_KERNEL_STREAM) {
             if (kgs_step(r->sim, pk.second) != KGS_OK) {
                 r->status = KGS_EDEVICE;
                 r->err = kgs_last_error(r->sim);
@@ -569,6 +653,10 @@ int run_big(kgs_server *s)
         } else {
             cls[r->cfg.dim * 2 + r->cfg.precision].push_back(pk);
         }
+    }
+    for (auto &kv : s2) {
+        const int rc = run_stream2d(s, kv.first.first, kv.first.second, kv.second);
+        if (rc != KGS_OK) return rc;
     }
     if (!cls.empty()) {
         const int bb = kgs::batch_block();
@@ -790,6 +878,10 @@ int kgs_server_submit(kgs_server *s, const kgs_config *cfg, const double *psi_re
     for (int a = 0; a < cfg->dim; ++a) r->points *= cfg->n;
     const size_t nb = static_cast<size_t>(r->points) * sizeof(double);
     r->bytes = bytes + static_cast<int64_t>(4 * nb);  // state + gathered result
+    // 2-D grids beyond one workgroup stream in the big lane: a second buffer
+    const int dk = kgs::default_kernel(*cfg);
+    if (cfg->dim == 2 && dk != KGS_KERNEL_RESIDENT && dk != KGS_KERNEL_STREAM)
+        r->bytes += kgs::state_bytes(*cfg);
     const double *src[4] = {psi_re, psi_im, u, v_t};
     if (mem == KGS_HOST) {
         r->host.reset(new (std::nothrow) double[4 * static_cast<size_t>(r->points)]);

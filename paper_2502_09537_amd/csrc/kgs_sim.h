@@ -46,5 +46,7 @@ void sim_destroy_pooled(kgs_sim *s);
 int default_kernel(const kgs_config &cfg);
 // Give the handle its second state buffer (ping-pong kernels) if it has none.
 int sim_ensure_state2(kgs_sim *s);
+// Bytes of one state buffer (8 planes) of a valid cfg.
+int64_t state_bytes(const kgs_config &cfg);
 
 }  // namespace kgs

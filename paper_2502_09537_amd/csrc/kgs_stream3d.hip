@@ -341,11 +341,11 @@ hipError_t launch_typed(const Geometry &g, const StreamShape &sh, const T *in, T
     const size_t lds = static_cast<size_t>(2) * S * 3 * NT * sizeof(T);
     if (threads > max_threads<T, S>() || items > 0x7fffffff || lds > 160 * 1024)
         return hipErrorInvalidValue;
-    // float64 four-sweep launches of the library's default tile are
-    // compiled with the tile fixed (measured on MI355X: 16x16 beats taller
-    // tiles of up to 768 threads, e.g. 16x28, at 256^3)
+    // four-sweep launches of the 16x16 tile are compiled with the tile fixed
+    // (measured on MI355X: 16x16 beats taller tiles of up to 768 threads,
+    // e.g. 16x28, at 256^3 float64)
     auto kern = first ? stream3d_kernel<T, S, true, 0, 0> : stream3d_kernel<T, S, false, 0, 0>;
-    if constexpr (sizeof(T) == 8 && S == 4) {
+    if constexpr (S == 4) {
         if (sh.tile_x == 16 && sh.tile_y == 16)
             kern = first ? stream3d_kernel<T, S, true, 16, 16> : stream3d_kernel<T, S, false, 16, 16>;
     }
