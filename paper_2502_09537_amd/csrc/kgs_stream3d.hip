@@ -213,8 +213,10 @@ __device__ __forceinline__ void pipeline_step(Pipe<T, S> &st, const Geo &g, T *l
             T *zo = out + static_cast<int64_t>(z) * plane_elems;  // uniform
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                *at(zo + (4 * c + q) * stride, g.colb) = res.f[q];
-                *at(zo + (4 * (c ^ 1) + q) * stride, g.colb) = oth.f[q];
+                // streaming stores: the next launch reads them back, this one
+                // never does, so they need not occupy L2
+                __builtin_nontemporal_store(res.f[q], at(zo + (4 * c + q) * stride, g.colb));
+                __builtin_nontemporal_store(oth.f[q], at(zo + (4 * (c ^ 1) + q) * stride, g.colb));
             }
         }
     }
