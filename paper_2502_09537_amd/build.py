@@ -28,7 +28,7 @@ HIP_FLAGS = [
     "-I", INCLUDE, "-I", CSRC,
 ]
 HOST_FLAGS = [
-    "-O2", "-fPIC", "-std=c++17", "-Wall", "-D__HIP_PLATFORM_AMD__",
+    "-O2", "-fPIC", "-std=c++17", "-Wall", "-pthread", "-D__HIP_PLATFORM_AMD__",
     "-I", os.path.join(ROCM, "include"), "-I", INCLUDE, "-I", CSRC,
 ]
 
@@ -71,7 +71,7 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("libkgs build failed:\n" + msg)
     tmp = LIB + ".tmp"
     link = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
-            "-L", os.path.join(ROCM, "lib"), "-lamdhip64", "-Wl,--no-undefined"]
+            "-L", os.path.join(ROCM, "lib"), "-lamdhip64", "-pthread", "-Wl,--no-undefined"]
     r = subprocess.run(link, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("libkgs link failed:\n" + " ".join(link) + "\n" + r.stdout + r.stderr)

@@ -19,9 +19,10 @@
 //     oversubscribed.
 // The host does not wait for the GPU in steady state: device memory comes
 // from a private pool in stream order, energies land in pinned slots, a
-// finished request's state is gathered on the device and copied to the host
-// on a copy stream once its event has passed, and at most kMaxAhead rounds
-// are queued ahead of the device on each lane.
+// finished request's state is gathered on the device and, once its event has
+// passed, copied to host memory by a worker thread on a stream of its own
+// (so the round loop keeps feeding the GPU while large results copy), and at
+// most kMaxAhead rounds are queued ahead of the device on each lane.
 //
 // Each request ends bitwise where running it alone ends: points of one
 // colour are independent and step boundaries store the state exactly as a
@@ -29,12 +30,15 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include <hip/hip_runtime_api.h>
@@ -77,8 +81,23 @@ struct Request {
     double *staging = nullptr;       // pooled gathered result during retirement
     hipEvent_t ev = nullptr;         // retirement complete on the device
     bool retiring = false;
+    bool copying = false;            // result handed to the copy worker
     bool dropped = false;            // cancelled while retiring
     std::string err;
+};
+
+// Copies of gathered results to host memory, done by a worker thread.
+struct CopyJob {
+    int64_t id;
+    double *src;  // pooled device buffer, released by the worker
+    size_t n;     // doubles
+};
+
+struct CopyDone {
+    int64_t id;
+    double *host;
+    hipError_t status;
+    double t;  // completion, seconds on the server clock
 };
 
 // Pinned host staging with a device twin, reused round-robin; a slot is
@@ -125,6 +144,15 @@ struct kgs_server {
     std::vector<hipEvent_t> spare_events;
     int64_t rounds = 0;
     std::string err;
+    // result-copy worker
+    std::thread copier;
+    hipStream_t copy_out = nullptr;
+    std::mutex mu;
+    std::condition_variable cv_jobs, cv_done;
+    std::deque<CopyJob> jobs;
+    std::deque<CopyDone> done;
+    int in_flight = 0;  // jobs queued or being copied
+    bool stop = false;
 };
 
 namespace {
@@ -393,24 +421,58 @@ void start_retire(kgs_server *s, Request *r)
     s->retiring.push_back(r->id);
 }
 
-// Complete a retirement whose event has passed: the result into host
-// memory, the energies from the pinned slot, the device memory released.
-void complete_retire(kgs_server *s, Request *r)
+// The copy worker: takes gathered results, copies them to new host arrays
+// on its own stream, returns the device buffers to the pool.
+void copy_worker(kgs_server *s)
 {
-    int32_t status = r->status;
-    if (status == KGS_OK && !r->dropped) {
-        const size_t n = 4 * static_cast<size_t>(r->points);
-        r->host.reset(new (std::nothrow) double[n]);
-        hipError_t e = r->host ? hipMemcpyAsync(r->host.get(), r->staging, n * sizeof(double),
-                                                hipMemcpyDeviceToHost, s->copy)
-                               : hipErrorOutOfMemory;
-        if (e == hipSuccess) e = hipStreamSynchronize(s->copy);
-        if (e != hipSuccess) {
-            status = status_of(e);
-            r->err = std::string("result copy: ") + hipGetErrorName(e);
-            r->host.reset();
-        }
+    if (hipSetDevice(s->device) != hipSuccess) {
     }
+    for (;;) {
+        CopyJob job;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_jobs.wait(lk, [&] { return s->stop || !s->jobs.empty(); });
+            if (s->jobs.empty()) return;  // stop requested and nothing left
+            job = s->jobs.front();
+            s->jobs.pop_front();
+        }
+        double *h = new (std::nothrow) double[job.n];
+        hipError_t e = h ? hipMemcpyAsync(h, job.src, job.n * sizeof(double), hipMemcpyDeviceToHost,
+                                          s->copy_out)
+                         : hipErrorOutOfMemory;
+        if (e == hipSuccess) e = hipStreamSynchronize(s->copy_out);
+        if (hipFreeAsync(job.src, s->copy_out) != hipSuccess) {
+        }
+        if (e != hipSuccess) {
+            delete[] h;
+            h = nullptr;
+        }
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->done.push_back({job.id, h, e, now_s() - s->t0});
+        --s->in_flight;
+        s->cv_done.notify_all();
+    }
+}
+
+// The final accounting of a retired request.
+void end_retire(kgs_server *s, Request *r, int32_t status, double t_done)
+{
+    r->retiring = false;
+    r->copying = false;
+    s->used -= r->bytes;
+    if (r->dropped) {
+        r->host.reset();  // already reported as cancelled
+        return;
+    }
+    r->state = status == KGS_OK ? KGS_REQ_DONE : KGS_REQ_FAILED;
+    r->status = status;
+    r->t_done = t_done;
+}
+
+// A retirement whose event has passed: energies from the pinned slot, the
+// gathered result handed to the copy worker (or dropped).
+void start_copy(kgs_server *s, Request *r)
+{
     if (r->slot >= 0) {
         // h^dim as kgs_energy forms it
         const double h = (r->cfg.hi - r->cfg.lo) / r->cfg.n;
@@ -422,37 +484,61 @@ void complete_retire(kgs_server *s, Request *r)
         s->free_slots.push_back(r->slot);
         r->slot = -1;
     }
-    if (status == KGS_OK && !(std::isfinite(r->e0) && std::isfinite(r->e1))) {
-        status = KGS_ENONFINITE;
-        r->err = "energy is not finite";
-    }
-    free_request_memory(s, r);
     give_event(s, r->ev);
     r->ev = nullptr;
-    r->retiring = false;
-    s->used -= r->bytes;
-    if (r->dropped) r->host.reset();  // already reported as cancelled
-    else finish(s, r, status == KGS_OK ? KGS_REQ_DONE : KGS_REQ_FAILED, status);
+    if (r->status == KGS_OK && !(std::isfinite(r->e0) && std::isfinite(r->e1))) {
+        r->status = KGS_ENONFINITE;
+        r->err = "energy is not finite";
+    }
+    if (r->status != KGS_OK || r->dropped || !r->staging) {
+        free_request_memory(s, r);
+        end_retire(s, r, r->status, now_s() - s->t0);
+        return;
+    }
+    CopyJob job{r->id, r->staging, 4 * static_cast<size_t>(r->points)};
+    r->staging = nullptr;  // the worker returns it to the pool
+    r->copying = true;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->jobs.push_back(job);
+    ++s->in_flight;
+    s->cv_jobs.notify_one();
 }
 
-// Complete the retirements whose events have passed; with `wait`, all.
+// Retirements: start the copies of those whose events have passed and
+// complete those whose copies are done; with `wait`, all of them.
 void collect(kgs_server *s, bool wait)
 {
-    std::vector<int64_t> still;
     for (int64_t id : s->retiring) {
         Request *r = s->reqs[id].get();
+        if (r->copying) continue;
         hipError_t q = hipSuccess;
         if (r->ev) q = wait ? hipEventSynchronize(r->ev) : hipEventQuery(r->ev);
-        if (q == hipErrorNotReady) {
-            still.push_back(id);
-            continue;
-        }
+        if (q == hipErrorNotReady) continue;
         if (q != hipSuccess && r->status == KGS_OK) {
             r->status = KGS_EDEVICE;
             r->err = std::string("retirement event: ") + hipGetErrorName(q);
         }
-        complete_retire(s, r);
+        start_copy(s, r);
     }
+    std::deque<CopyDone> done;
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        if (wait) s->cv_done.wait(lk, [&] { return s->in_flight == 0; });
+        done.swap(s->done);
+    }
+    for (const CopyDone &d : done) {
+        Request *r = s->reqs[d.id].get();
+        int32_t status = r->status;
+        if (d.status != hipSuccess) {
+            status = status_of(d.status);
+            r->err = std::string("result copy: ") + hipGetErrorName(d.status);
+        }
+        r->host.reset(d.host);
+        end_retire(s, r, status, d.t);
+    }
+    std::vector<int64_t> still;
+    for (int64_t id : s->retiring)
+        if (s->reqs[id]->retiring) still.push_back(id);
     s->retiring.swap(still);
 }
 
@@ -827,6 +913,7 @@ int kgs_server_create(const kgs_server_config *cfg, void *stream, kgs_server **o
     for (int l = 0; l < 2 && e == hipSuccess; ++l)
         e = hipStreamCreateWithFlags(&s->lane[l], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy_out, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_submit, hipEventDisableTiming);
     if (e == hipSuccess) {
         hipMemPoolProps props;
@@ -848,6 +935,12 @@ int kgs_server_create(const kgs_server_config *cfg, void *stream, kgs_server **o
         return sfail(nullptr, KGS_EDEVICE, msg);
     }
     s->t0 = now_s();
+    try {
+        s->copier = std::thread(copy_worker, s);
+    } catch (...) {
+        kgs_server_free(s);
+        return sfail(nullptr, KGS_ENOMEM, "could not start the copy thread");
+    }
     *out = s;
     return KGS_OK;
 }
@@ -1031,8 +1124,16 @@ int kgs_server_free(kgs_server *s)
     int rc = KGS_OK;
     if (hipSetDevice(s->device) != hipSuccess) rc = KGS_EDEVICE;
     collect(s, true);
+    if (s->copier.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->stop = true;
+        }
+        s->cv_jobs.notify_all();
+        s->copier.join();
+    }
     for (auto &kv : s->reqs) free_request_memory(s, kv.second.get());
-    for (hipStream_t st : {s->lane[0], s->lane[1], s->copy})
+    for (hipStream_t st : {s->lane[0], s->lane[1], s->copy, s->copy_out})
         if (st && hipStreamSynchronize(st) != hipSuccess) rc = KGS_EDEVICE;
     if (hipStreamSynchronize(s->user) != hipSuccess) rc = KGS_EDEVICE;
     for (hipEvent_t e : s->ahead) give_event(s, e);
@@ -1056,7 +1157,7 @@ int kgs_server_free(kgs_server *s)
     }
     if (s->ev_submit && hipEventDestroy(s->ev_submit) != hipSuccess) {
     }
-    for (hipStream_t st : {s->lane[0], s->lane[1], s->copy})
+    for (hipStream_t st : {s->lane[0], s->lane[1], s->copy, s->copy_out})
         if (st && hipStreamDestroy(st) != hipSuccess) {
         }
     if (s->pool && hipMemPoolDestroy(s->pool) != hipSuccess) rc = KGS_EDEVICE;
