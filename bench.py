@@ -190,10 +190,10 @@ def bench_batched(args):
            "value": results[best]["updates_per_s"], "unit": "lattice-point updates/s",
            "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": results[best]["ms"] / steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64" if prec == workloads.FP64 else "f32-state/f64-math", "data": "synthetic",
+           "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"batched: 64 2-D instances n in {{128..1024 step 64}}, "
                                   f"params U[0.5,2], {steps} steps, {args.precision}",
-                      "points": points, "best_mode": best},
+                      "points": points, "state": args.precision, "best_mode": best},
            "modes": results, "bitwise_identical_across_modes": identical,
            "speedup_vs_per_instance": results[best]["updates_per_s"] /
            results["per_instance"]["updates_per_s"]}
@@ -220,9 +220,10 @@ def bench_serving(args):
     work = sum(r.problem.points * r.problem.steps for r in reqs)
     out = {"metric": "served solves/s with p50/p99 latency", "unit": "solves/s", "n_gpus": 1,
            "steps": None, "warmup": 0, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64+f32 mix", "data": "synthetic",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"serving: {args.requests} Poisson requests at {args.rate}/s, "
                                   "1-D/2-D/3-D mix, fp32/fp64, steps U[100,2000]",
+                      "state": "fp64 and fp32 requests",
                       "budget_gb": args.budget_gb, "steps_per_round": args.round_steps,
                       "round_work": args.round_work,
                       "lattice_updates_total": work}}
@@ -433,11 +434,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32-state/f64-math",
+        "dtype": "f64",  # the arithmetic; the state precision is in config
         "data": "synthetic",
         "config": {"workload": f"kgs3d n={p.n}^3 box [-8,8)^3 tau={p.tau} "
                                f"{args.precision} state, {args.steps} DP-AVF2 steps",
-                   "points": p.points, "kernel": int(info.kernel),
+                   "points": p.points, "state": args.precision, "kernel": int(info.kernel),
                    "tile": [tun.tile_x, tun.tile_y, tun.chunk, tun.steps_per_launch]
                    if info.kernel == kgs.KGS_KERNEL_STREAM else None,
                    "parallelism": "1 GPU"},
