@@ -98,7 +98,19 @@ def cpu_baseline(problem, steps):
     return {"value": problem.points * steps / dt, "unit": "lattice-point updates/s",
             "cores": 1, "kind": "oracle",
             "sample": f"{problem.dim}-D n={problem.n} same initial data, {steps} DP-AVF2 steps "
-                      f"of the full grid, float64, {dt:.1f} s"}
+                      f"of the full grid, float64, {dt:.1f} s",
+            "host_cpu": host_cpu(), "host_threads": os.cpu_count()}
+
+
+def host_cpu() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def rel_errors(got, ref):
@@ -124,6 +136,25 @@ def fp32_vs_fp64(kgs, problems, states, steps):
         e = rel_errors(got, ref)
         worst = {k: max(worst[k], e[k]) for k in worst}
     return worst
+
+
+def device_copy_gbs(torch, stream, mib):
+    """Bytes read plus written per second by a plain device-to-device copy of
+    `mib` MiB (best of 5)."""
+    a = torch.ones(mib << 17, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = 1e30
+    for _ in range(5):
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record(stream)
+        b.copy_(a)
+        s1.record(stream)
+        torch.cuda.synchronize()
+        best = min(best, s0.elapsed_time(s1) / 1e3)
+    n = a.numel() * 8
+    del a, b
+    return 2 * n / best / 1e9
 
 
 def _timed_ms(torch, stream, fn):
@@ -227,11 +258,18 @@ def bench_serving(args):
                       "budget_gb": args.budget_gb, "steps_per_round": args.round_steps,
                       "round_work": args.round_work,
                       "lattice_updates_total": work}}
+    # "saturated" submits every request at once: its makespan gives the
+    # continuous server's capacity on this mix, and the offered load is
+    # rho = offered updates/s / that capacity
     modes = {"continuous": dict(max_active=0, steps_per_round=args.round_steps,
                                 round_work=args.round_work),
-             "one_at_a_time": dict(max_active=1, steps_per_round=0)}
+             "one_at_a_time": dict(max_active=1, steps_per_round=0),
+             "saturated": dict(max_active=0, steps_per_round=args.round_steps,
+                               round_work=args.round_work)}
+    offered = work / (reqs[-1].arrival - reqs[0].arrival)
     check_ids = []
     for mode, kw in modes.items():
+        burst = mode == "saturated"
         srv = kgs.Server(budget_bytes=args.budget_gb << 30, **kw)
         keep = []
         ids = []
@@ -240,7 +278,7 @@ def bench_serving(args):
         offset = srv.stats().now  # server clock at t_start
         while True:
             now = time.perf_counter() - t_start
-            while i < len(reqs) and reqs[i].arrival <= now:
+            while i < len(reqs) and (burst or reqs[i].arrival <= now):
                 p = reqs[i].problem
                 f = workloads.gaussian_fields_torch(p)
                 rid = srv.submit_device(kgs.config_of(p), *f, p.steps)
@@ -260,14 +298,20 @@ def bench_serving(args):
         for rid, j in ids:
             info = srv.poll(rid)
             assert info.state == kgs.KGS_REQ_DONE, (mode, j, info.state, info.status)
-            lat.append(info.t_done - (reqs[j].arrival + offset))
+            lat.append(info.t_done - ((0.0 if burst else reqs[j].arrival) + offset))
             done_t.append(info.t_done - offset)
         lat = np.array(lat)
-        span = max(done_t) - reqs[0].arrival
+        span = max(done_t) - (0.0 if burst else reqs[0].arrival)
+        if burst:
+            out[mode] = {"makespan_s": span, "capacity_updates_per_s": work / span,
+                         "solves_per_s": len(reqs) / span}
+            out["offered_load_rho"] = offered / (work / span)
+            srv.close()
+            continue
         out[mode] = {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
                      "mean_s": float(lat.mean()), "solves_per_s": len(reqs) / span,
                      "lattice_updates_per_s": work / span, "makespan_s": span,
-                     "offered_updates_per_s": work / (reqs[-1].arrival - reqs[0].arrival),
+                     "offered_updates_per_s": offered,
                      "rounds": int(srv.stats().rounds)}
         if mode == "continuous":
             # results in the mix equal results alone (a sample of small requests)
@@ -458,6 +502,14 @@ def main():
         s32.close()
         out["fp32_max_rel_err_vs_fp64"] = fp32_vs_fp64(kgs, [p], [got], args.steps)
         del got
+    if traffic:
+        # actual HBM traffic rate of the dominant kernel, against the peak and
+        # against what a plain device copy reaches on this GPU
+        out["roofline"]["traffic_GBs"] = traffic / avg_launch_s / 1e9
+        copy_gbs = device_copy_gbs(torch, stream, 1024)
+        out["roofline"]["copy_GBs"] = copy_gbs
+        out["roofline"]["traffic_frac_of_peak"] = traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS
+        out["roofline"]["traffic_frac_of_copy"] = traffic / avg_launch_s / 1e9 / copy_gbs
     if args.calibrate_copy:
         a = torch.empty(args.calibrate_copy << 17, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)

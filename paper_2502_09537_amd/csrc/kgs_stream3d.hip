@@ -56,6 +56,11 @@ __device__ __forceinline__ int wrap(int v, int m)
     return v < 0 ? v + m : v;
 }
 
+// Row pitch of a published plane in LDS: the block width made odd, so that
+// a column of the block (rows one pitch apart), which the ring threads
+// read, falls in distinct banks.
+__host__ __device__ constexpr int lds_pitch(int bx) { return bx | 1; }
+
 // Largest workgroup per instantiation: the four-sweep pipeline keeps 16
 // planes of FIFO per thread and needs more than 128 VGPRs, so at most 3
 // waves per SIMD (12 per workgroup); a compiled-in tile has exactly its
@@ -82,6 +87,7 @@ struct Pipe {
 // Thread geometry shared by all steps of a workgroup.
 struct Geo {
     int NT;              // threads with a column of the block
+    int NL;              // LDS slots per published plane (odd row pitch)
     int wave;            // first thread of this thread's wave
     int need[5];         // stage j runs on threads below need[S - 1 - j]
     bool live, in_tile;  // has a column / writes its column
@@ -147,7 +153,7 @@ __device__ __forceinline__ void pipeline_step(Pipe<T, S> &st, const Geo &g, T *l
                                               int steps, int &z_load, const Coef &k)
 {
     constexpr int HX = (S + 1) / 2, HY = S;
-    const int NT = TX ? (TX + 2 * HX) * (TY + 2 * HY) : g.NT;
+    const int NL = TX ? lds_pitch(TX + 2 * HX) * (TY + 2 * HY) : g.NL;
     constexpr int s0 = PH % 3, s1 = (PH + 2) % 3, s2 = (PH + 1) % 3;  // steps p, p-1, p-2
     // the blue plane of step p arrived in Bn; fetch step p + 1 (red plane
     // into the slot of step p - 2, which no stage reads any more)
@@ -165,7 +171,7 @@ __device__ __forceinline__ void pipeline_step(Pipe<T, S> &st, const Geo &g, T *l
     // of the step (the plane moves back by one when the colour flips)
     const int o = (z_load + g.y + 1) & 1;
     const int i_xm = o ? g.i_xm1 : g.i_xm0, i_xp = o ? g.i_xp1 : g.i_xp0;
-    const T *pub = lds + static_cast<size_t>((p - 1) & 1) * S * 3 * NT;
+    const T *pub = lds + static_cast<size_t>((p - 1) & 1) * S * 3 * NL;
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         if (p < 2 * j + 2) continue;  // pipeline not yet filled for stage j
@@ -174,11 +180,11 @@ __device__ __forceinline__ void pipeline_step(Pipe<T, S> &st, const Geo &g, T *l
         // level-j neighbours: z -/+ 1 from registers, in-plane from LDS
         const Vals<T> &up = (j == 0) ? st.B[s0] : st.F[j > 0 ? j - 1 : 0][s0];
         const Vals<T> &dn = (j == 0) ? st.B[s2] : st.F[j > 0 ? j - 1 : 0][s2];
-        const T *pl0 = pub + j * 3 * NT;
+        const T *pl0 = pub + j * 3 * NL;
         double sum[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const T *pl = pl0 + q * NT;
+            const T *pl = pl0 + q * NL;
             double a = static_cast<double>(dn.f[q]);
             a = a + static_cast<double>(up.f[q]);
             a = a + static_cast<double>(pl[g.i_ym]);
@@ -223,13 +229,13 @@ __device__ __forceinline__ void pipeline_step(Pipe<T, S> &st, const Geo &g, T *l
     z_load = z_load + 1 == n ? 0 : z_load + 1;
     // publish the newest plane of every level that a stage reads next step
     if (g.live) {
-        T *pw = lds + static_cast<size_t>(p & 1) * S * 3 * NT;
+        T *pw = lds + static_cast<size_t>(p & 1) * S * 3 * NL;
 #pragma unroll
-        for (int q = 0; q < 3; ++q) pw[q * NT + g.i_self] = st.B[s0].f[q];
+        for (int q = 0; q < 3; ++q) pw[q * NL + g.i_self] = st.B[s0].f[q];
 #pragma unroll
         for (int j = 1; j < S; ++j) {
 #pragma unroll
-            for (int q = 0; q < 3; ++q) pw[(j * 3 + q) * NT + g.i_self] = st.F[j - 1][s0].f[q];
+            for (int q = 0; q < 3; ++q) pw[(j * 3 + q) * NL + g.i_self] = st.F[j - 1][s0].f[q];
         }
     }
     __syncthreads();
@@ -252,8 +258,10 @@ stream3d_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t stride, i
     const int H = n >> 1;
     const int BX = tile_x + 2 * HX;
     const int BY = tile_y + 2 * HY;
+    const int PX = lds_pitch(BX);
     Geo g;
     g.NT = BX * BY;
+    g.NL = PX * BY;
     const int tid = threadIdx.x;
     g.live = tid < g.NT;
     g.wave = tid & ~63;
@@ -282,13 +290,13 @@ stream3d_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t stride, i
                 xu < H && yu < n;
     // in-plane neighbour slots in the block (clamped: edge threads compute
     // values nobody valid depends on)
-    g.i_self = lty * BX + ltx;
-    g.i_ym = max(lty - 1, 0) * BX + ltx;
-    g.i_yp = min(lty + 1, BY - 1) * BX + ltx;
-    g.i_xm0 = lty * BX + max(ltx - 1, 0);
+    g.i_self = lty * PX + ltx;
+    g.i_ym = max(lty - 1, 0) * PX + ltx;
+    g.i_yp = min(lty + 1, BY - 1) * PX + ltx;
+    g.i_xm0 = lty * PX + max(ltx - 1, 0);
     g.i_xm1 = g.i_self;
     g.i_xp0 = g.i_self;
-    g.i_xp1 = lty * BX + min(ltx + 1, BX - 1);
+    g.i_xp1 = lty * PX + min(ltx + 1, BX - 1);
 
     const int64_t plane_elems = static_cast<int64_t>(n) * H;
     g.colb = static_cast<uint32_t>(g.y * H + xh) * static_cast<uint32_t>(sizeof(T));
@@ -335,12 +343,13 @@ hipError_t launch_typed(const Geometry &g, const StreamShape &sh, const T *in, T
     const int H = g.n / 2;
     const int BX = sh.tile_x + 2 * HX, BY = sh.tile_y + 2 * HY;
     const int NT = BX * BY;
+    const int NL = lds_pitch(BX) * BY;
     const int threads = (NT + 63) / 64 * 64;
     const int tiles_x = (H + sh.tile_x - 1) / sh.tile_x;
     const int tiles_y = (g.n + sh.tile_y - 1) / sh.tile_y;
     const int chunks = (g.n + sh.chunk - 1) / sh.chunk;
     const int64_t items = static_cast<int64_t>(tiles_x) * tiles_y * chunks;
-    const size_t lds = static_cast<size_t>(2) * S * 3 * NT * sizeof(T);
+    const size_t lds = static_cast<size_t>(2) * S * 3 * NL * sizeof(T);
     if (threads > max_threads<T, S>() || items > 0x7fffffff || lds > 160 * 1024)
         return hipErrorInvalidValue;
     // four-sweep launches of the 16x16 tile are compiled with the tile fixed
@@ -375,7 +384,7 @@ bool stream3d_shape_ok(const Geometry &g, const StreamShape &sh, int elem_bytes)
     const int NT = BX * BY;
     const int limit = S == 4 ? max_threads<float, 4>() : max_threads<float, 2>();
     if ((NT + 63) / 64 * 64 > limit) return false;
-    return static_cast<size_t>(2) * S * 3 * NT * elem_bytes <= 160 * 1024;
+    return static_cast<size_t>(2) * S * 3 * lds_pitch(BX) * BY * elem_bytes <= 160 * 1024;
 }
 
 hipError_t launch_stream3d(const Geometry &g, int precision, const StreamShape &sh, int stages,
