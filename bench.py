@@ -15,6 +15,7 @@ import argparse
 import json
 import os
 import sys
+import statistics
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -47,6 +48,8 @@ def parse():
                     help="pick the launch configuration with kgs_autotune before timing")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also time a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="3-D: repetitions of the K-step call after the timed one (median reported)")
     ap.add_argument("--requests", type=int, default=120, help="serving: number of requests")
     ap.add_argument("--rate", type=float, default=50.0, help="serving: mean arrivals per second")
     ap.add_argument("--budget-gb", type=int, default=64, help="serving: device memory budget")
@@ -439,6 +442,16 @@ def main():
     wall = t1 - t0
     kernel_ms = start.elapsed_time(stop)
 
+    # the same K-step call repeated: the spread of the timed region
+    reps = []
+    for _ in range(args.repeats):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        sim.step(args.steps)
+        b.record(stream)
+        torch.cuda.synchronize()
+        reps.append(a.elapsed_time(b))
+
     # the dominant kernel's own average duration: a kgs_step call of K steps
     # is K/spl streaming launches (or 2K sweeps) plus one closing sweep, so
     # time 2- and 4-step calls and take the difference
@@ -492,6 +505,8 @@ def main():
                      "algorithmic_bytes_per_launch": algo_per_launch},
         "energy_rel_drift": abs(e1 - e0) / abs(e0),
         "kernel_ms": kernel_ms,
+        "repeats_ms": reps,
+        "median_updates_per_s": updates / (statistics.median(reps) / 1e3) if reps else None,
     }
     if args.precision == "fp32":
         # the float32 state's error after the timed number of steps, against
