@@ -7,7 +7,7 @@ grid (both colour sweeps); the timed region runs exactly --steps of them
 followed by one energy evaluation (the drift report), with the state already
 resident in HBM.  Prints one JSON line.
 
-    python bench.py [--steps 200] [--warmup 20] [--precision fp64|fp32]
+    python bench.py [--steps 200] [--warmup 200] [--precision fp64|fp32]
 """
 from __future__ import annotations
 
@@ -25,7 +25,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_3d256.json")
 KERNEL_SOURCES = ("kgs_stream3d.hip", "kgs_sweep.hip", "kgs_sweep_body.h", "kgs_point.h",
-                  "kgs_internal.h")
+                  "kgs_internal.h", "kgs_layout.h")
 ALGO_BYTES = {"fp64": 64, "fp32": 32}  # read + write (P, Q, U, V) once per point-step
 METRIC = "lattice-point updates/s + % HBM roofline (3D 256³ FP64); served p50/p99"
 
@@ -38,7 +38,9 @@ def parse():
                          "serving: Poisson request stream; 1d/2d: the 1-D and 2-D configurations")
     ap.add_argument("--steps", type=int, default=None,
                     help="timed DP-AVF2 steps (default: the workload's own count)")
-    ap.add_argument("--warmup", type=int, default=20)
+    # the GPU needs tens of milliseconds of load to reach its steady clock:
+    # 200 steps of the 3-D grid take about 50 ms
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--kernel", choices=["auto", "sweep", "stream"], default="auto")

@@ -181,7 +181,7 @@ kgs_tuning default_tuning(const kgs_config &c)
         t.kernel = KGS_KERNEL_STREAM;
         t.chunk = 64;
         while (t.chunk > 8 && kgs::stream2d_tasks(c.n, t.chunk) < 1024) t.chunk /= 2;
-    } else if (c.dim == 3 && c.precision == KGS_FP64 && c.n >= 96) {
+    } else if (c.dim == 3 && c.n >= 96) {
         t.kernel = KGS_KERNEL_STREAM;
         const int64_t tiles = static_cast<int64_t>((c.n / 2 + 15) / 16) * ((c.n + 15) / 16);
         while (t.chunk > 8 && tiles * ((c.n + t.chunk - 1) / t.chunk) < 200) t.chunk /= 2;

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kgs_internal.h"
+#include "kgs_layout.h"
 
 namespace kgs {
 namespace {
@@ -107,16 +108,19 @@ __device__ __forceinline__ double density(const T *__restrict__ base, int64_t st
     const int o = (s + DIM + 1 + c) & 1;
     int xp = xh + o;
     if (xp >= H) xp -= H;
-    const T *own = base + static_cast<int64_t>(4 * c) * stride;
-    const T *oth = base + static_cast<int64_t>(4 * (c ^ 1)) * stride;
+    const T *oth_pq = pair_plane(base, stride, c ^ 1, PAIR_PQ);
+    const T *oth_uv = pair_plane(base, stride, c ^ 1, PAIR_UV);
     const int64_t i = row * H + xh;
-    const double p = ld(own + F_P * stride + i), q = ld(own + F_Q * stride + i);
-    const double u = ld(own + F_U * stride + i), v = ld(own + F_V * stride + i);
+    const Pair<T> own_pq = ld_pair(pair_plane(base, stride, c, PAIR_PQ), i);
+    const Pair<T> own_uv = ld_pair(pair_plane(base, stride, c, PAIR_UV), i);
+    const double p = own_pq.x, q = own_pq.y;
+    const double u = own_uv.x, v = own_uv.y;
     double gp = 0.0, gq = 0.0, gu = 0.0;
     auto add = [&](int64_t j) {
-        const double dp = ld(oth + F_P * stride + j) - p;
-        const double dq = ld(oth + F_Q * stride + j) - q;
-        const double du = ld(oth + F_U * stride + j) - u;
+        const Pair<T> o_pq = ld_pair(oth_pq, j);
+        const double dp = static_cast<double>(o_pq.x) - p;
+        const double dq = static_cast<double>(o_pq.y) - q;
+        const double du = ld(oth_uv + 2 * j) - u;
         gp = gp + dp * dp;
         gq = gq + dq * dq;
         gu = gu + du * du;

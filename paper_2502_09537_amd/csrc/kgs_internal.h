@@ -1,11 +1,16 @@
 // Internal interface between the host side of the library (kgs_api.cpp,
 // compiled by the host compiler) and the HIP kernels (*.hip, gfx950).
 //
-// Device layout of a simulation ("colour-split structure of arrays"):
-//   8 planes = 2 colours (0 = red, 1 = blue) x 4 fields (P = Re psi,
-//   Q = Im psi, U = u, V = u_t), plane (colour, field) at
-//   base + (4*colour + field) * stride elements.
-//   Within a plane a point is addressed as row * H + xh, where H = n/2,
+// Device layout of a simulation ("colour-split pair planes"):
+//   2 colours (0 = red, 1 = blue) x 2 pair planes of 2*stride elements:
+//   (P, Q) = (Re psi, Im psi) at base + 4*colour*stride and (U, V) = (u, u_t)
+//   at base + (4*colour + 2)*stride, the two values of point t at elements
+//   2t and 2t + 1 of its pair plane.  Field f (F_P, F_Q, F_U, F_V) of point
+//   t of colour c is therefore element (4c + (f & 2))*stride + 2t + (f & 1),
+//   and the whole state is 8*stride elements.  A pair is one vector access;
+//   the neighbours of a point, which need P, Q and U of the other colour,
+//   read a (P, Q) pair and U alone.
+//   Point t = row * H + xh, where H = n/2,
 //   row = i0 (2-D) or i0*n + i1 (3-D) or 0 (1-D) enumerates the grid lines
 //   along the last (fastest) axis x, and xh = x/2 is x compressed to the
 //   points of one colour.  In row r with index sum s (i0 + i1 in 3-D, i0 in
@@ -68,7 +73,7 @@ struct Geometry {
     int half;        // n / 2
     int64_t rows;    // n^(dim-1)
     int64_t count;   // points per colour = rows * half
-    int64_t stride;  // elements between planes (count rounded up)
+    int64_t stride;  // count rounded up to 64; a pair plane spans 2*stride elements
 };
 
 // Shape of the 3-D z-streaming kernel: output tile of tile_y rows x tile_x

@@ -1,0 +1,64 @@
+// Device access to the pair-plane state layout described in kgs_internal.h:
+// per colour c, the plane of (P, Q) pairs starts at base + 4c*stride and
+// the plane of (U, V) pairs at base + (4c + 2)*stride; point t of a pair
+// plane occupies elements 2t and 2t + 1.  One vector access moves both
+// values of a pair (16 bytes in float64, 8 in float32).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kgs_internal.h"
+
+namespace kgs {
+
+template <typename T>
+struct PairOf;
+template <>
+struct PairOf<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct PairOf<float> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+template <typename T>
+using Pair = typename PairOf<T>::type;
+
+enum PairKind { PAIR_PQ = 0, PAIR_UV = 1 };
+
+// First element of pair plane `pk` (PAIR_PQ or PAIR_UV) of colour c.
+template <typename T>
+__device__ __forceinline__ T *pair_plane(T *base, int64_t stride, int c, int pk)
+{
+    return base + static_cast<int64_t>(4 * c + 2 * pk) * stride;
+}
+
+template <typename T>
+__device__ __forceinline__ const T *pair_plane(const T *base, int64_t stride, int c, int pk)
+{
+    return base + static_cast<int64_t>(4 * c + 2 * pk) * stride;
+}
+
+template <typename T>
+__device__ __forceinline__ Pair<T> ld_pair(const T *plane, int64_t t)
+{
+    return *reinterpret_cast<const Pair<T> *>(plane + 2 * t);
+}
+
+template <typename T>
+__device__ __forceinline__ void st_pair(T *plane, int64_t t, T a, T b)
+{
+    Pair<T> v;
+    v.x = a;
+    v.y = b;
+    *reinterpret_cast<Pair<T> *>(plane + 2 * t) = v;
+}
+
+// The first value of a pair (P of a (P, Q) pair, U of a (U, V) pair) alone.
+template <typename T>
+__device__ __forceinline__ T ld_first(const T *plane, int64_t t)
+{
+    return plane[2 * t];
+}
+
+}  // namespace kgs

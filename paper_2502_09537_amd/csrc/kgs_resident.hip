@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kgs_internal.h"
+#include "kgs_layout.h"
 #include "kgs_point.h"
 #include "kgs_sweep_body.h"
 
@@ -128,9 +129,12 @@ resident_kernel(ResidentMember one, const ResidentMember *__restrict__ list,
         neighbours<DIM>(t, m.n, p.nrow[j], p.nx[j]);
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-#pragma unroll
-            for (int f = 0; f < 3; ++f) lds[(3 * c + f) * C + t] = g[(4 * c + f) * S + t];
-            p.v[c][j] = g[(4 * c + F_V) * S + t];
+            const Pair<T> pq = ld_pair(pair_plane(g, S, c, PAIR_PQ), t);
+            const Pair<T> uv = ld_pair(pair_plane(g, S, c, PAIR_UV), t);
+            lds[(3 * c + F_P) * C + t] = pq.x;
+            lds[(3 * c + F_Q) * C + t] = pq.y;
+            lds[(3 * c + F_U) * C + t] = uv.x;
+            p.v[c][j] = uv.y;
         }
     }
     __syncthreads();
@@ -153,9 +157,9 @@ resident_kernel(ResidentMember one, const ResidentMember *__restrict__ list,
         if (t >= C) continue;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-#pragma unroll
-            for (int f = 0; f < 3; ++f) g[(4 * c + f) * S + t] = lds[(3 * c + f) * C + t];
-            g[(4 * c + F_V) * S + t] = p.v[c][j];
+            st_pair(pair_plane(g, S, c, PAIR_PQ), t, lds[(3 * c + F_P) * C + t],
+                    lds[(3 * c + F_Q) * C + t]);
+            st_pair(pair_plane(g, S, c, PAIR_UV), t, lds[(3 * c + F_U) * C + t], p.v[c][j]);
         }
     }
 }

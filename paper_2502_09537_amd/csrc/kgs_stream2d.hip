@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kgs_internal.h"
+#include "kgs_layout.h"
 #include "kgs_point.h"
 
 namespace kgs {
@@ -45,6 +46,23 @@ template <typename T, int S>
 struct Pipe {
     Vals<T> R[3], B[3], Bn, F[S - 1][3];
 };
+
+// The four values of point pt of colour c: two pair loads.
+template <typename T>
+__device__ __forceinline__ Vals<T> load_vals(const T *base, int64_t stride, int c, int64_t pt)
+{
+    const Pair<T> pq = ld_pair(pair_plane(base, stride, c, PAIR_PQ), pt);
+    const Pair<T> uv = ld_pair(pair_plane(base, stride, c, PAIR_UV), pt);
+    return Vals<T>{{pq.x, pq.y, uv.x, uv.y}};
+}
+
+template <typename T>
+__device__ __forceinline__ void store_vals(T *base, int64_t stride, int c, int64_t pt,
+                                           const Vals<T> &x)
+{
+    st_pair(pair_plane(base, stride, c, PAIR_PQ), pt, x.f[0], x.f[1]);
+    st_pair(pair_plane(base, stride, c, PAIR_UV), pt, x.f[2], x.f[3]);
+}
 
 __device__ __forceinline__ int wrap(int v, int m)
 {
@@ -75,12 +93,9 @@ __device__ __forceinline__ void step2d(Pipe<T, S> &st, const Task &t, const T *_
     st.B[s0] = st.Bn;
     if (p + 1 < steps) {
         const int yn = y_load + 1 == n ? 0 : y_load + 1;
-        const T *row = in + static_cast<int64_t>(yn) * H + t.xh;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            st.R[s2].f[q] = row[q * stride];
-            st.Bn.f[q] = row[(4 + q) * stride];
-        }
+        const int64_t pt = static_cast<int64_t>(yn) * H + t.xh;
+        st.R[s2] = load_vals(in, stride, RED, pt);
+        st.Bn = load_vals(in, stride, BLUE, pt);
     }
     // x-offset of the updated colour in the updated rows: the same for every
     // stage of the step
@@ -126,13 +141,9 @@ __device__ __forceinline__ void step2d(Pipe<T, S> &st, const Task &t, const T *_
             // final level S at row z: colour c from this stage, the other
             // colour from stage S-2 one step ago
             const int z = wrap(y_load - S, n);
-            const Vals<T> &oth = st.F[S - 2][s1];
-            T *row = out + static_cast<int64_t>(z) * H + t.xh;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                row[(4 * c + q) * stride] = res.f[q];
-                row[(4 * (c ^ 1) + q) * stride] = oth.f[q];
-            }
+            const int64_t pt = static_cast<int64_t>(z) * H + t.xh;
+            store_vals(out, stride, c, pt, res);
+            store_vals(out, stride, c ^ 1, pt, st.F[S - 2][s1]);
         }
     }
     y_load = y_load + 1 == n ? 0 : y_load + 1;
@@ -198,12 +209,9 @@ stream2d_kernel(Stream2dMember one, const Stream2dMember *__restrict__ list, int
     const int steps = t.L + 2 * S;
     int y_load = wrap(t.y0 - S, t.n);
     {
-        const T *row = in + static_cast<int64_t>(y_load) * t.H + t.xh;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            st.R[0].f[q] = row[q * stride];
-            st.Bn.f[q] = row[(4 + q) * stride];
-        }
+        const int64_t pt = static_cast<int64_t>(y_load) * t.H + t.xh;
+        st.R[0] = load_vals(in, stride, RED, pt);
+        st.Bn = load_vals(in, stride, BLUE, pt);
     }
     for (int p = 0; p < steps; p += 3) {
         step2d<T, S, 0>(st, t, in, out, stride, p, steps, y_load, first, k);

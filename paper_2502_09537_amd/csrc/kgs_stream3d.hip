@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kgs_internal.h"
+#include "kgs_layout.h"
 #include "kgs_point.h"
 
 namespace kgs {
@@ -48,6 +49,32 @@ template <typename T>
 __device__ __forceinline__ const T *at(const T *base, uint32_t byte_offset)
 {
     return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_offset);
+}
+
+// The four values of a column of colour c in the z-plane whose pair planes
+// start at zb2 (uniform), at byte offset colb2 inside each pair plane: two
+// pair loads.
+template <typename T>
+__device__ __forceinline__ Vals<T> load_col(const T *zb2, int64_t stride, int c, uint32_t colb2)
+{
+    const Pair<T> pq = *reinterpret_cast<const Pair<T> *>(at(pair_plane(zb2, stride, c, PAIR_PQ), colb2));
+    const Pair<T> uv = *reinterpret_cast<const Pair<T> *>(at(pair_plane(zb2, stride, c, PAIR_UV), colb2));
+    return Vals<T>{{pq.x, pq.y, uv.x, uv.y}};
+}
+
+// Streaming stores: the next launch reads them back, this one never does,
+// so they need not occupy L2.
+template <typename T>
+__device__ __forceinline__ void store_col(T *zb2, int64_t stride, int c, uint32_t colb2,
+                                          const Vals<T> &x)
+{
+    Pair<T> pq, uv;
+    pq.x = x.f[0];
+    pq.y = x.f[1];
+    uv.x = x.f[2];
+    uv.y = x.f[3];
+    __builtin_nontemporal_store(pq, reinterpret_cast<Pair<T> *>(at(pair_plane(zb2, stride, c, PAIR_PQ), colb2)));
+    __builtin_nontemporal_store(uv, reinterpret_cast<Pair<T> *>(at(pair_plane(zb2, stride, c, PAIR_UV), colb2)));
 }
 
 __device__ __forceinline__ int wrap(int v, int m)
@@ -92,7 +119,7 @@ struct Geo {
     int need[5];         // stage j runs on threads below need[S - 1 - j]
     bool live, in_tile;  // has a column / writes its column
     int y;               // wrapped row of the column
-    uint32_t colb;       // byte offset of the column inside a plane (< 2^31)
+    uint32_t colb2;      // byte offset of the column inside a z-plane of a pair plane (< 2^31)
     int i_self, i_ym, i_yp;
     int i_xm0, i_xm1, i_xp0, i_xp1;  // x-neighbour slots for x-offset o = 0, 1
 };
@@ -160,12 +187,9 @@ __device__ __forceinline__ void pipeline_step(Pipe<T, S> &st, const Geo &g, T *l
     st.B[s0] = st.Bn;
     if (g.live && p + 1 < steps) {
         const int zn = z_load + 1 == n ? 0 : z_load + 1;
-        const T *zb = in + static_cast<int64_t>(zn) * plane_elems;  // uniform
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            st.R[s2].f[q] = *at(zb + q * stride, g.colb);
-            st.Bn.f[q] = *at(zb + (4 + q) * stride, g.colb);
-        }
+        const T *zb2 = in + 2 * static_cast<int64_t>(zn) * plane_elems;  // uniform
+        st.R[s2] = load_col(zb2, stride, RED, g.colb2);
+        st.Bn = load_col(zb2, stride, BLUE, g.colb2);
     }
     // x-offset of the updated colour in this row: the same for every stage
     // of the step (the plane moves back by one when the colour flips)
@@ -215,15 +239,9 @@ __device__ __forceinline__ void pipeline_step(Pipe<T, S> &st, const Geo &g, T *l
             // final level S at plane z: colour c from this stage, the other
             // colour from stage S-2 one step ago
             const int z = wrap(z_load - S, n);  // n may be smaller than S
-            const Vals<T> &oth = st.F[S - 2][s1];
-            T *zo = out + static_cast<int64_t>(z) * plane_elems;  // uniform
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                // streaming stores: the next launch reads them back, this one
-                // never does, so they need not occupy L2
-                __builtin_nontemporal_store(res.f[q], at(zo + (4 * c + q) * stride, g.colb));
-                __builtin_nontemporal_store(oth.f[q], at(zo + (4 * (c ^ 1) + q) * stride, g.colb));
-            }
+            T *zo2 = out + 2 * static_cast<int64_t>(z) * plane_elems;  // uniform
+            store_col(zo2, stride, c, g.colb2, res);
+            store_col(zo2, stride, c ^ 1, g.colb2, st.F[S - 2][s1]);
         }
     }
     z_load = z_load + 1 == n ? 0 : z_load + 1;
@@ -299,7 +317,7 @@ stream3d_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t stride, i
     g.i_xp1 = lty * PX + min(ltx + 1, BX - 1);
 
     const int64_t plane_elems = static_cast<int64_t>(n) * H;
-    g.colb = static_cast<uint32_t>(g.y * H + xh) * static_cast<uint32_t>(sizeof(T));
+    g.colb2 = static_cast<uint32_t>(g.y * H + xh) * static_cast<uint32_t>(2 * sizeof(T));
 
     Pipe<T, S> st;
     {
@@ -316,12 +334,9 @@ stream3d_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t stride, i
     int z_load = wrap(z0 - S, n);  // plane loaded (consumed) at step p
     // the first plane: red into the slot of step 0, blue into Bn
     if (g.live) {
-        const T *zb = in + static_cast<int64_t>(z_load) * plane_elems;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            st.R[0].f[q] = *at(zb + q * stride, g.colb);
-            st.Bn.f[q] = *at(zb + (4 + q) * stride, g.colb);
-        }
+        const T *zb2 = in + 2 * static_cast<int64_t>(z_load) * plane_elems;
+        st.R[0] = load_col(zb2, stride, RED, g.colb2);
+        st.Bn = load_col(zb2, stride, BLUE, g.colb2);
     }
     const int64_t pe = plane_elems;
     for (int p = 0; p < steps; p += 3) {
@@ -377,8 +392,9 @@ bool stream3d_shape_ok(const Geometry &g, const StreamShape &sh, int elem_bytes)
         return false;
     if (sh.steps != 1 && sh.steps != 2) return false;
     if (sh.tile_x < 1 || sh.tile_y < 1 || sh.chunk < 1) return false;
-    // per-thread offsets inside a plane are 32-bit byte offsets
-    if (static_cast<int64_t>(g.n) * (g.n / 2) * elem_bytes >= (int64_t(1) << 31)) return false;
+    // per-thread offsets inside a z-plane of a pair plane are 32-bit byte
+    // offsets
+    if (2 * static_cast<int64_t>(g.n) * (g.n / 2) * elem_bytes >= (int64_t(1) << 31)) return false;
     const int S = 2 * sh.steps;
     const int BX = sh.tile_x + 2 * ((S + 1) / 2), BY = sh.tile_y + 2 * S;
     const int NT = BX * BY;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kgs_internal.h"
+#include "kgs_layout.h"
 #include "kgs_point.h"
 #include "kgs_sweep_body.h"
 
@@ -48,11 +49,10 @@ scatter_kernel(T *__restrict__ base, int64_t stride, int n, int64_t total,
     int c;
     int64_t ci;
     split_index<DIM>(idx, n, c, ci);
-    T *p = base + static_cast<int64_t>(4 * c) * stride + ci;
-    p[F_P * stride] = static_cast<T>(P[idx]);
-    p[F_Q * stride] = static_cast<T>(Q[idx]);
-    p[F_U * stride] = static_cast<T>(U[idx]);
-    p[F_V * stride] = static_cast<T>(V[idx]);
+    st_pair(pair_plane(base, stride, c, PAIR_PQ), ci, static_cast<T>(P[idx]),
+            static_cast<T>(Q[idx]));
+    st_pair(pair_plane(base, stride, c, PAIR_UV), ci, static_cast<T>(U[idx]),
+            static_cast<T>(V[idx]));
 }
 
 template <int DIM, typename T>
@@ -66,11 +66,12 @@ gather_kernel(const T *__restrict__ base, int64_t stride, int n, int64_t total,
     int c;
     int64_t ci;
     split_index<DIM>(idx, n, c, ci);
-    const T *p = base + static_cast<int64_t>(4 * c) * stride + ci;
-    P[idx] = static_cast<double>(p[F_P * stride]);
-    Q[idx] = static_cast<double>(p[F_Q * stride]);
-    U[idx] = static_cast<double>(p[F_U * stride]);
-    V[idx] = static_cast<double>(p[F_V * stride]);
+    const Pair<T> pq = ld_pair(pair_plane(base, stride, c, PAIR_PQ), ci);
+    const Pair<T> uv = ld_pair(pair_plane(base, stride, c, PAIR_UV), ci);
+    P[idx] = static_cast<double>(pq.x);
+    Q[idx] = static_cast<double>(pq.y);
+    U[idx] = static_cast<double>(uv.x);
+    V[idx] = static_cast<double>(uv.y);
 }
 
 bool geometry_ok(const Geometry &g)

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kgs_internal.h"
+#include "kgs_layout.h"
 #include "kgs_point.h"
 
 namespace kgs {
@@ -50,27 +51,45 @@ __device__ __forceinline__ RowInfo<DIM> row_info(int64_t row, int n)
     return r;
 }
 
-// Neighbour sum of one other-colour plane f at point (row, xh) whose own
-// x-offset is o, in the fixed axis order (axis 0 -, axis 0 +, ..., x -, x +).
-template <int DIM, typename T>
-__device__ __forceinline__ double nb_sum(const T *__restrict__ f, const RowInfo<DIM> &r,
-                                         int64_t row, int xh, int xm, int xp, int H)
+// Other-colour point indices of the 2*DIM neighbours of (row, xh) in the
+// fixed axis order (axis 0 -, axis 0 +, ..., x -, x +), given the x
+// neighbours xm, xp.
+template <int DIM>
+__device__ __forceinline__ void nb_index(const RowInfo<DIM> &r, int64_t row, int xh, int xm,
+                                         int xp, int H, int64_t *j)
 {
-    double acc;
     if (DIM == 1) {
-        acc = ld(f + xm);
-        acc = acc + ld(f + xp);
+        j[0] = xm;
+        j[1] = xp;
     } else {
-        acc = ld(f + r.nb[0] * H + xh);
-        acc = acc + ld(f + r.nb[1] * H + xh);
+        j[0] = r.nb[0] * H + xh;
+        j[1] = r.nb[1] * H + xh;
         if (DIM == 3) {
-            acc = acc + ld(f + r.nb[2] * H + xh);
-            acc = acc + ld(f + r.nb[3] * H + xh);
+            j[2] = r.nb[2] * H + xh;
+            j[3] = r.nb[3] * H + xh;
         }
-        acc = acc + ld(f + row * H + xm);
-        acc = acc + ld(f + row * H + xp);
+        j[2 * DIM - 2] = row * H + xm;
+        j[2 * DIM - 1] = row * H + xp;
     }
-    return acc;
+}
+
+// Neighbour sums of P, Q (one pair load per neighbour) and U (U alone) of
+// the other colour, each added in the fixed axis order.
+template <int DIM, typename T>
+__device__ __forceinline__ void nb_sums(const T *__restrict__ pq, const T *__restrict__ uv,
+                                        const int64_t *j, double &sr, double &si, double &su)
+{
+    Pair<T> a = ld_pair(pq, j[0]);
+    sr = static_cast<double>(a.x);
+    si = static_cast<double>(a.y);
+    su = ld(uv + 2 * j[0]);
+#pragma unroll
+    for (int m = 1; m < 2 * DIM; ++m) {
+        a = ld_pair(pq, j[m]);
+        sr = sr + static_cast<double>(a.x);
+        si = si + static_cast<double>(a.y);
+        su = su + ld(uv + 2 * j[m]);
+    }
 }
 
 // One point of one colour sweep: point t of colour `colour` in the plane set
@@ -89,20 +108,18 @@ __device__ __forceinline__ void sweep_one(T *__restrict__ base, int64_t stride, 
     int xp = xh + o;
     if (xp >= H) xp -= H;
 
-    T *own = base + static_cast<int64_t>(4 * colour) * stride;
-    const T *oth = base + static_cast<int64_t>(4 * (colour ^ 1)) * stride;
-    const double sr = nb_sum<DIM>(oth + F_P * stride, r, row, xh, xm, xp, H);
-    const double si = nb_sum<DIM>(oth + F_Q * stride, r, row, xh, xm, xp, H);
-    const double su = nb_sum<DIM>(oth + F_U * stride, r, row, xh, xm, xp, H);
-    double pr = ld(own + F_P * stride + t);
-    double pi = ld(own + F_Q * stride + t);
-    double u = ld(own + F_U * stride + t);
-    double v = ld(own + F_V * stride + t);
+    int64_t j[2 * DIM];
+    nb_index<DIM>(r, row, xh, xm, xp, H, j);
+    double sr, si, su;
+    nb_sums<DIM>(pair_plane(base, stride, colour ^ 1, PAIR_PQ),
+                 pair_plane(base, stride, colour ^ 1, PAIR_UV), j, sr, si, su);
+    T *own_pq = pair_plane(base, stride, colour, PAIR_PQ);
+    T *own_uv = pair_plane(base, stride, colour, PAIR_UV);
+    const Pair<T> pq = ld_pair(own_pq, t), uv = ld_pair(own_uv, t);
+    double pr = pq.x, pi = pq.y, u = uv.x, v = uv.y;
     sweep_point<KIND, T>(k, pr, pi, u, v, sr, si, su);
-    own[F_P * stride + t] = static_cast<T>(pr);
-    own[F_Q * stride + t] = static_cast<T>(pi);
-    own[F_U * stride + t] = static_cast<T>(u);
-    own[F_V * stride + t] = static_cast<T>(v);
+    st_pair(own_pq, t, static_cast<T>(pr), static_cast<T>(pi));
+    st_pair(own_uv, t, static_cast<T>(u), static_cast<T>(v));
 }
 
 

@@ -101,12 +101,17 @@ def test_null_arguments(L):
 
 
 def test_required_bytes(L):
-    # 3-D float64 grids run the ping-pong streaming kernel by default: two states
+    # 3-D grids of n >= 96 run the ping-pong streaming kernel by default in
+    # both precisions: two states
     cfg = good(dim=3, n=256)
     state = 8 * (256 ** 3 // 2) * 8
     assert 2 * state <= kgs.required_bytes(cfg) < 2 * state + (1 << 20)
     cfg32 = good(dim=3, n=256, precision=kgs.KGS_FP32)
-    assert state // 2 <= kgs.required_bytes(cfg32) < state // 2 + (1 << 20)
+    assert state <= kgs.required_bytes(cfg32) < state + (1 << 20)
+    # below n = 96 they sweep in place: one state
+    cfg64s = good(dim=3, n=64)
+    small = 8 * (64 ** 3 // 2) * 8
+    assert small <= kgs.required_bytes(cfg64s) < small + (1 << 20)
     # 2-D float64 grids of n >= 512 stream too (two states); float32 sweeps (one)
     cfg2 = good(dim=2, n=1024)
     state2 = 8 * (1024 ** 2 // 2) * 8
