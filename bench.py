@@ -379,7 +379,7 @@ def bench_small_dims(args):
     wall = time.perf_counter() - t0
     sim.close()
     names = {kgs.KGS_KERNEL_SWEEP: "sweep", kgs.KGS_KERNEL_STREAM: "stream",
-             kgs.KGS_KERNEL_RESIDENT: "resident"}
+             kgs.KGS_KERNEL_RESIDENT: "resident", kgs.KGS_KERNEL_TILE: "tile"}
     out = {"metric": "lattice-point updates/s", "value": p.points * steps / wall,
            "unit": "lattice-point updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
            "ms_per_step": wall * 1e3 / steps, "higher_is_better": True, "scaling": "weak",

@@ -973,7 +973,8 @@ int kgs_server_submit(kgs_server *s, const kgs_config *cfg, const double *psi_re
     r->bytes = bytes + static_cast<int64_t>(4 * nb);  // state + gathered result
     // 2-D grids beyond one workgroup stream in the big lane: a second buffer
     const int dk = kgs::default_kernel(*cfg);
-    if (cfg->dim == 2 && dk != KGS_KERNEL_RESIDENT && dk != KGS_KERNEL_STREAM)
+    if (cfg->dim == 2 && dk != KGS_KERNEL_RESIDENT && dk != KGS_KERNEL_STREAM &&
+        dk != KGS_KERNEL_TILE)
         r->bytes += kgs::state_bytes(*cfg);
     const double *src[4] = {psi_re, psi_im, u, v_t};
     if (mem == KGS_HOST) {

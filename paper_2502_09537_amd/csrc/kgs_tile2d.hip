@@ -1,0 +1,232 @@
+// 2-D tiled kernel: S consecutive colour sweeps (S/2 DP-AVF2 steps) of a 2-D
+// grid in one launch, each workgroup holding one tile of the grid plus a halo
+// in LDS, reading the state from one buffer and writing it to another.
+//
+// Why: a 2-D grid of moderate size (1024^2 is 0.5 M points per colour) has
+// too few rows for the y-streaming kernel to give every SIMD more than about
+// one wave, and a streaming task spends 2S pipeline steps filling and
+// draining.  Here a workgroup loads a block of TY + 2S rows by TXC + 2*HX
+// compressed positions of both colours (HX = ceil(S/2): each sweep reaches
+// one point further along every axis, half a compressed position along x),
+// runs the S sweeps in LDS with one barrier after each, and writes the TY x
+// TXC interior.  Neighbours outside the block are replaced by the nearest
+// block position; the values this spoils stay in the halo, which is never
+// written.  Sweep j runs only on the positions that a later sweep still
+// needs: the interior grown by S-1-j rows and ceil((S-1-j)/2) compressed
+// positions.
+//
+// P, Q and U of both colours live in LDS (the neighbours read them); u_t of
+// the points a thread owns stays in its registers.  The neighbour sums use
+// the order of the one-sweep kernel (axis 0 -, +, x -, +) and values are
+// rounded to the storage type at the same places, so the state is bitwise
+// that of every other kernel.
+#include <hip/hip_runtime.h>
+
+#include "kgs_internal.h"
+#include "kgs_layout.h"
+#include "kgs_point.h"
+
+namespace kgs {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ int wrap(int v, int m)
+{
+    v %= m;
+    return v < 0 ? v + m : v;
+}
+
+// The positions p = threadIdx.x + j kThreads (j < PPT) a thread owns.
+template <typename T, int PPT>
+struct Owned {
+    T v[2][PPT];        // u_t [colour][point]
+    int ly[PPT], lx[PPT];
+    int ym[PPT], yp[PPT];      // block positions one row down / up
+    int xm[PPT][2], xp[PPT][2];  // other-colour x neighbours [point][colour]
+};
+
+template <typename T, int PPT, int KIND, int COLOUR>
+__device__ __forceinline__ void tile_sweep(T *lds, int NB, const Coef &k, Owned<T, PPT> &w,
+                                           int y_lo, int y_hi, int x_lo, int x_hi)
+{
+    const T *op = lds + 3 * (COLOUR ^ 1) * NB, *oq = op + NB, *ou = oq + NB;
+    T *mp = lds + 3 * COLOUR * NB, *mq = mp + NB, *mu = mq + NB;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int p = threadIdx.x + j * kThreads;
+        if (p >= NB || w.ly[j] < y_lo || w.ly[j] >= y_hi || w.lx[j] < x_lo || w.lx[j] >= x_hi)
+            continue;
+        const int a0 = w.ym[j], a1 = w.yp[j], a2 = w.xm[j][COLOUR], a3 = w.xp[j][COLOUR];
+        double sr = static_cast<double>(op[a0]);
+        sr = sr + static_cast<double>(op[a1]);
+        sr = sr + static_cast<double>(op[a2]);
+        sr = sr + static_cast<double>(op[a3]);
+        double si = static_cast<double>(oq[a0]);
+        si = si + static_cast<double>(oq[a1]);
+        si = si + static_cast<double>(oq[a2]);
+        si = si + static_cast<double>(oq[a3]);
+        double su = static_cast<double>(ou[a0]);
+        su = su + static_cast<double>(ou[a1]);
+        su = su + static_cast<double>(ou[a2]);
+        su = su + static_cast<double>(ou[a3]);
+        double pr = static_cast<double>(mp[p]);
+        double pi = static_cast<double>(mq[p]);
+        double u = static_cast<double>(mu[p]);
+        double v = static_cast<double>(w.v[COLOUR][j]);
+        sweep_point<KIND, T>(k, pr, pi, u, v, sr, si, su);
+        mp[p] = static_cast<T>(pr);
+        mq[p] = static_cast<T>(pi);
+        mu[p] = static_cast<T>(u);
+        w.v[COLOUR][j] = static_cast<T>(v);
+    }
+}
+
+template <typename T, int S, int PPT, bool FIRST>
+__global__ void __launch_bounds__(kThreads)
+tile2d_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t stride, int n, int tiles_x,
+              int ty, int txc, Coef k)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T *lds = reinterpret_cast<T *>(lds_raw);
+    constexpr int HY = S, HX = (S + 1) / 2;
+    const int H = n >> 1;
+    const int BY = ty + 2 * HY, BX = txc + 2 * HX, NB = BY * BX;
+    const int tile = blockIdx.x;
+    const int x0 = (tile % tiles_x) * txc, y0 = (tile / tiles_x) * ty;
+
+    Owned<T, PPT> w;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int p = threadIdx.x + j * kThreads;
+        const int q = p < NB ? p : 0;
+        const int ly = q / BX, lx = q - (q / BX) * BX;
+        w.ly[j] = ly;
+        w.lx[j] = lx;
+        w.ym[j] = (ly > 0 ? ly - 1 : 0) * BX + lx;
+        w.yp[j] = (ly < BY - 1 ? ly + 1 : BY - 1) * BX + lx;
+        // the block starts at an even point x, so a block-local position
+        // has the parity of its global one; a row's colour offset follows
+        // the parity of its global row index
+        const int yu = y0 - HY + ly;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int o = (yu + 3 + c) & 1;
+            const int xm = lx - 1 + o, xp = lx + o;
+            w.xm[j][c] = ly * BX + (xm > 0 ? xm : 0);
+            w.xp[j][c] = ly * BX + (xp < BX - 1 ? xp : BX - 1);
+        }
+        w.v[0][j] = w.v[1][j] = T(0);
+        if (p < NB) {
+            const int64_t pt = static_cast<int64_t>(wrap(yu, n)) * H + wrap(x0 - HX + lx, H);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const Pair<T> pq = ld_pair(pair_plane(in, stride, c, PAIR_PQ), pt);
+                const Pair<T> uv = ld_pair(pair_plane(in, stride, c, PAIR_UV), pt);
+                lds[(3 * c) * NB + p] = pq.x;
+                lds[(3 * c + 1) * NB + p] = pq.y;
+                lds[(3 * c + 2) * NB + p] = uv.x;
+                w.v[c][j] = uv.y;
+            }
+        }
+    }
+    __syncthreads();
+    // sweep j updates the interior grown by m = S-1-j rows and ceil(m/2)
+    // compressed positions
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int m = S - 1 - j, mx = (m + 1) / 2;
+        const int y_lo = HY - m, y_hi = HY + ty + m, x_lo = HX - mx, x_hi = HX + txc + mx;
+        if (j & 1) {
+            tile_sweep<T, PPT, PASS_B_FULL, BLUE>(lds, NB, k, w, y_lo, y_hi, x_lo, x_hi);
+        } else if (FIRST && j == 0) {
+            tile_sweep<T, PPT, PASS_R_BASE, RED>(lds, NB, k, w, y_lo, y_hi, x_lo, x_hi);
+        } else {
+            tile_sweep<T, PPT, PASS_R_ADJ_BASE, RED>(lds, NB, k, w, y_lo, y_hi, x_lo, x_hi);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int p = threadIdx.x + j * kThreads;
+        const int ly = w.ly[j], lx = w.lx[j];
+        const int yu = y0 - HY + ly, xu = x0 - HX + lx;
+        if (p >= NB || ly < HY || ly >= HY + ty || lx < HX || lx >= HX + txc || yu >= n || xu >= H)
+            continue;
+        const int64_t pt = static_cast<int64_t>(yu) * H + xu;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            st_pair(pair_plane(out, stride, c, PAIR_PQ), pt, lds[(3 * c) * NB + p],
+                    lds[(3 * c + 1) * NB + p]);
+            st_pair(pair_plane(out, stride, c, PAIR_UV), pt, lds[(3 * c + 2) * NB + p], w.v[c][j]);
+        }
+    }
+}
+
+template <typename T, int S, int PPT>
+hipError_t launch_ppt(const Geometry &g, int ty, int txc, const T *in, T *out, bool first,
+                      const Coef &k, hipStream_t s)
+{
+    constexpr int HY = S, HX = (S + 1) / 2;
+    const int NB = (ty + 2 * HY) * (txc + 2 * HX);
+    const int tiles_x = (g.half + txc - 1) / txc;
+    const int64_t tiles = static_cast<int64_t>(tiles_x) * ((g.n + ty - 1) / ty);
+    const size_t lds = static_cast<size_t>(6) * NB * sizeof(T);
+    auto kern = first ? tile2d_kernel<T, S, PPT, true> : tile2d_kernel<T, S, PPT, false>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(tiles)), dim3(kThreads), lds, s, in, out,
+                       g.stride, g.n, tiles_x, ty, txc, k);
+    return hipGetLastError();
+}
+
+template <typename T, int S>
+hipError_t launch_typed(const Geometry &g, int ty, int txc, const T *in, T *out, bool first,
+                        const Coef &k, hipStream_t s)
+{
+    const int NB = (ty + 2 * S) * (txc + 2 * ((S + 1) / 2));
+    if (NB <= 2 * kThreads) return launch_ppt<T, S, 2>(g, ty, txc, in, out, first, k, s);
+    if (NB <= 4 * kThreads) return launch_ppt<T, S, 4>(g, ty, txc, in, out, first, k, s);
+    return launch_ppt<T, S, 8>(g, ty, txc, in, out, first, k, s);
+}
+
+}  // namespace
+
+int64_t tile2d_tiles(const Geometry &g, int ty, int txc)
+{
+    if (ty < 1 || txc < 1) return 0;
+    return static_cast<int64_t>((g.half + txc - 1) / txc) * ((g.n + ty - 1) / ty);
+}
+
+bool tile2d_shape_ok(const Geometry &g, int ty, int txc, int stages, int elem_bytes)
+{
+    if (g.dim != 2 || g.n < 2 || (g.n & 1) || g.count != static_cast<int64_t>(g.n) * (g.n / 2))
+        return false;
+    if ((stages != 2 && stages != 4) || ty < 1 || txc < 1) return false;
+    const int NB = (ty + 2 * stages) * (txc + 2 * ((stages + 1) / 2));
+    if (NB > 8 * kThreads) return false;
+    if (static_cast<size_t>(6) * NB * elem_bytes > 160 * 1024) return false;
+    return tile2d_tiles(g, ty, txc) <= 0x7fffffff;
+}
+
+hipError_t launch_tile2d(const Geometry &g, int precision, int stages, int ty, int txc,
+                         const void *in, void *out, bool first, const Coef &k, hipStream_t s)
+{
+    const int eb = precision == 0 ? 8 : 4;
+    if (!in || !out || in == out || !tile2d_shape_ok(g, ty, txc, stages, eb))
+        return hipErrorInvalidValue;
+    if (precision == 0) {
+        const double *i = static_cast<const double *>(in);
+        double *o = static_cast<double *>(out);
+        return stages == 2 ? launch_typed<double, 2>(g, ty, txc, i, o, first, k, s)
+                           : launch_typed<double, 4>(g, ty, txc, i, o, first, k, s);
+    }
+    const float *i = static_cast<const float *>(in);
+    float *o = static_cast<float *>(out);
+    return stages == 2 ? launch_typed<float, 2>(g, ty, txc, i, o, first, k, s)
+                       : launch_typed<float, 4>(g, ty, txc, i, o, first, k, s);
+}
+
+}  // namespace kgs

@@ -44,6 +44,20 @@ std::vector<kgs_tuning> candidates(const kgs_sim *s)
                 t.steps_per_launch = spl;
                 out.push_back(t);
             }
+        const int eb = s->cfg.precision == KGS_FP32 ? 4 : 8;
+        const int tiles[][3] = {{8, 8, 2},   {8, 16, 2},  {16, 16, 2}, {16, 32, 2},
+                                {32, 16, 2}, {32, 32, 2}, {16, 16, 1}, {32, 32, 1}};
+        for (const auto &tl : tiles) {
+            if (!kgs::tile2d_shape_ok(s->geo, tl[0], tl[1], 2 * tl[2], eb)) continue;
+            kgs_tuning t;
+            std::memset(&t, 0, sizeof(t));
+            t.kernel = KGS_KERNEL_TILE;
+            t.block = 256;
+            t.tile_y = tl[0];
+            t.tile_x = tl[1];
+            t.steps_per_launch = tl[2];
+            out.push_back(t);
+        }
     }
     if (s->cfg.dim == 3) {
         const int eb = s->cfg.precision == KGS_FP32 ? 4 : 8;

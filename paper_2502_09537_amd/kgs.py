@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkgs.so")
 KGS_OK, KGS_EINVAL, KGS_EODDN, KGS_ESINGULAR, KGS_ENOMEM, KGS_EDEVICE, KGS_ENONFINITE = range(7)
 KGS_FP64, KGS_FP32 = 0, 1
 KGS_HOST, KGS_DEVICE = 0, 1
-KGS_KERNEL_AUTO, KGS_KERNEL_SWEEP, KGS_KERNEL_STREAM, KGS_KERNEL_RESIDENT = range(4)
+KGS_KERNEL_AUTO, KGS_KERNEL_SWEEP, KGS_KERNEL_STREAM, KGS_KERNEL_RESIDENT, KGS_KERNEL_TILE = range(5)
 
 # every function declared in include/kgs.h
 EXPORTS = (

@@ -112,9 +112,13 @@ def test_required_bytes(L):
     cfg64s = good(dim=3, n=64)
     small = 8 * (64 ** 3 // 2) * 8
     assert small <= kgs.required_bytes(cfg64s) < small + (1 << 20)
-    # 2-D float64 grids of n >= 512 stream too (two states); float32 sweeps (one)
+    # 2-D grids beyond the resident kernel run the tiled kernel (n < 2048) or
+    # stream (n >= 2048), both between two states, in both precisions
     cfg2 = good(dim=2, n=1024)
     state2 = 8 * (1024 ** 2 // 2) * 8
     assert 2 * state2 <= kgs.required_bytes(cfg2) < 2 * state2 + (1 << 20)
     cfg2f = good(dim=2, n=1024, precision=kgs.KGS_FP32)
-    assert state2 // 2 <= kgs.required_bytes(cfg2f) < state2 // 2 + (1 << 20)
+    assert state2 <= kgs.required_bytes(cfg2f) < state2 + (1 << 20)
+    cfg2s = good(dim=2, n=64)  # resident: one state
+    small2 = 8 * (64 ** 2 // 2) * 8
+    assert small2 <= kgs.required_bytes(cfg2s) < small2 + (1 << 20)

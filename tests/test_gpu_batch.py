@@ -188,7 +188,8 @@ def test_2d_members_stepped_alone_between_streamed_batch_runs():
              workloads.random_problem(2, 150, seed=62, tau=0.02, amp=0.5)]
     say("2-D alone + batched")
     sims = [kgs.simulation_from_problem(p) for p in probs]
-    assert sims[0].tuning.kernel == kgs.KGS_KERNEL_STREAM  # swaps its buffers
+    # both run the ping-pong tiled kernel alone: each swaps its buffers
+    assert [s.tuning.kernel for s in sims] == [kgs.KGS_KERNEL_TILE] * 2
     b = kgs.Batch(sims)
     b.step(4)
     sims[0].step(3)

@@ -1,0 +1,104 @@
+"""GPU: the 2-D tiled kernel (a tile plus halo of both colours in LDS, 1 or 2
+DP-AVF2 steps per launch, ping-pong buffers) gives bitwise the state of the
+one-sweep-per-launch kernel for tiles that divide the grid, ragged edge
+tiles, tiles wider or taller than the grid, every points-per-thread class,
+and matches the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_09537_amd import kgs, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def tuning(kernel, ty=32, tx=16, spl=2):
+    t = kgs.KgsTuning()
+    t.kernel = kernel
+    t.block = 256
+    t.tile_y, t.tile_x, t.steps_per_launch = ty, tx, spl
+    t.chunk = 16
+    return t
+
+
+def run(p, calls, t):
+    sim = kgs.simulation_from_problem(p, tuning=t)
+    try:
+        assert sim.info().kernel == t.kernel
+        for c in calls:
+            sim.step(c)
+        return sim.read_state(), sim.energy()
+    finally:
+        sim.close()
+
+
+CASES = [
+    # n, tile rows, tile points of one colour, steps per launch, step calls
+    (2, 1, 1, 2, [3]),          # tile and halo wrap around a 2x2 grid
+    (4, 3, 1, 1, [2, 1]),
+    (30, 7, 5, 2, [5]),         # ragged in both directions
+    (64, 32, 16, 2, [3, 4]),    # 2 points per thread
+    (64, 16, 16, 1, [3]),
+    (130, 32, 16, 2, [3]),      # odd number of points per row and colour
+    (250, 48, 24, 2, [2, 3]),   # 4 points per thread
+    (256, 40, 32, 2, [5]),      # 8 points per thread
+    (256, 64, 32, 2, [2]),      # too many points for one workgroup: rejected
+    (1024, 32, 16, 2, [3]),
+]
+
+
+@pytest.mark.parametrize("prec", [workloads.FP64, workloads.FP32])
+@pytest.mark.parametrize("n,ty,tx,spl,calls", CASES)
+def test_tile2d_equals_sweep_bitwise(n, ty, tx, spl, calls, prec):
+    p = workloads.random_problem(2, n, seed=700 + n + ty, tau=0.02, amp=0.5, precision=prec)
+    say("tile2d vs sweep", n, ty, tx, spl, calls, prec)
+    sim = kgs.simulation_from_problem(p)
+    try:
+        sim.tuning = tuning(kgs.KGS_KERNEL_TILE, ty, tx, spl)
+    except kgs.KgsError:
+        # the block does not fit one workgroup (LDS or points per thread)
+        assert (ty + 4 * spl) * (tx + 2 * spl) > 2048 or \
+            6 * (ty + 4 * spl) * (tx + 2 * spl) * (8 if prec == workloads.FP64 else 4) > 160 * 1024
+        sim.close()
+        return
+    sim.close()
+    (a, ea) = run(p, calls, tuning(kgs.KGS_KERNEL_TILE, ty, tx, spl))
+    (b, eb) = run(p, [sum(calls)], tuning(kgs.KGS_KERNEL_SWEEP))
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    assert ea == eb
+
+
+def test_tile2d_matches_oracle():
+    p = workloads.config_2d(n=160, steps=60)
+    say("tile2d vs oracle")
+    ((psi, u, v), _) = run(p, [p.steps], tuning(kgs.KGS_KERNEL_TILE, 32, 16, 2))
+    ref = oracle.State.from_fields(p.psi, p.u, p.v)
+    oracle.step(oracle.Grid(2, p.n, p.lo, p.hi, p.kappa1, p.kappa2, p.mu, p.gamma), p.tau, ref,
+                p.steps)
+    scale = max(np.max(np.abs(f)) for f in ref.arrays())
+    for x, y in zip((psi.real, psi.imag, u, v), ref.arrays()):
+        assert np.max(np.abs(x - y)) <= 1e-12 * scale
+
+
+def test_tile2d_rejects_bad_shapes():
+    p = workloads.random_problem(2, 64, seed=1)
+    sim = kgs.simulation_from_problem(p)
+    for bad in (tuning(kgs.KGS_KERNEL_TILE, 0, 16, 2), tuning(kgs.KGS_KERNEL_TILE, 16, 0, 2),
+                tuning(kgs.KGS_KERNEL_TILE, 16, 16, 3), tuning(kgs.KGS_KERNEL_TILE, 200, 100, 2)):
+        with pytest.raises(kgs.KgsError):
+            sim.tuning = bad
+    sim.close()
+    for dim in (1, 3):
+        q = workloads.random_problem(dim, 8, seed=1)
+        sim = kgs.simulation_from_problem(q)
+        with pytest.raises(kgs.KgsError):
+            sim.tuning = tuning(kgs.KGS_KERNEL_TILE, 4, 4, 1)
+        sim.close()
