@@ -40,7 +40,12 @@ struct BatchClass {
     kgs::Stream2dMember *d_s2 = nullptr, *h_s2 = nullptr;
     int64_t s2_tasks = 0;
     int s2_chunk = 0;
+    // members all below n = 2048: the tiled kernel (tiles of s2_ty rows x
+    // s2_tx points of one colour) instead of the y-streaming kernel
+    bool s2_tile = false;
+    int s2_ty = 0, s2_tx = 0;
 };
+
 
 }  // namespace
 
@@ -193,8 +198,11 @@ hipError_t enqueue_uniform(kgs_batch *b, int64_t nsteps)
         std::memset(&none, 0, sizeof(none));
         for (size_t i = 0; i < stages.size(); ++i) {
             const kgs::Stream2dMember *list = c.d_s2 + (i == 0 ? 0 : (i % 2 ? 2 * nm : nm));
-            hipError_t e = kgs::launch_stream2d(c.precision, stages[i], none, list, nm, c.s2_tasks,
-                                                b->own);
+            hipError_t e = c.s2_tile ? kgs::launch_tile2d_list(c.precision, stages[i], c.s2_ty,
+                                                               c.s2_tx, none, list, nm, c.s2_tasks,
+                                                               b->own, i == 0 ? 1 : 0)
+                                     : kgs::launch_stream2d(c.precision, stages[i], none, list, nm,
+                                                            c.s2_tasks, b->own);
             if (e != hipSuccess) return e;
         }
         hipError_t e = kgs::launch_batch_sweep(c.dim, c.precision, c.d_members, nm, c.blocks,
@@ -369,9 +377,11 @@ int kgs_batch_create(kgs_sim *const *sims, int32_t count, void *stream, kgs_batc
             }
             c.blocks = blocks;
             if (c.dim == 2) {
-                // 2-D streaming for uniform runs: every member needs its
-                // second buffer; the row chunk gives >= 2048 tasks (waves)
-                // where the members allow it
+                // 2-D runs of several steps between two buffers (every
+                // member needs its second buffer): the y-streaming kernel
+                // with a row chunk that gives >= 2048 tasks (waves) where
+                // the members allow it, or the tiled kernel when that chunk
+                // is short and all members are below n = 2048
                 c.s2 = true;
                 const size_t nm = c.members.size();
                 for (size_t i = 0; i < nm && code == KGS_OK; ++i)
@@ -388,6 +398,16 @@ int kgs_batch_create(kgs_sim *const *sims, int32_t count, void *stream, kgs_batc
                 };
                 while (chunk > 8 && tasks(chunk) < 2048) chunk /= 2;
                 c.s2_chunk = chunk;
+                // tiles when the members are too few for long streaming
+                // chunks (measured: 64 uneven grids of n <= 1024 stream at
+                // chunk 64 1.2x faster than they run tiles)
+                c.s2_tile = chunk < 32;
+                std::vector<int> ns(nm);
+                for (size_t i = 0; i < nm; ++i) {
+                    ns[i] = b->sims[c.members[i]]->geo.n;
+                    if (ns[i] >= 2048) c.s2_tile = false;
+                }
+                kgs::tile2d_group_shape(ns.data(), static_cast<int>(nm), c.s2_ty, c.s2_tx);
                 const size_t s2bytes = 3 * nm * sizeof(kgs::Stream2dMember);
                 if ((e = hipMalloc(reinterpret_cast<void **>(&c.d_s2), s2bytes)) != hipSuccess ||
                     (e = hipHostMalloc(reinterpret_cast<void **>(&c.h_s2), s2bytes,
@@ -405,11 +425,13 @@ int kgs_batch_create(kgs_sim *const *sims, int32_t count, void *stream, kgs_batc
                         m.task_begin = tb;
                         m.k = x->coef;
                         m.n = x->geo.n;
-                        m.chunk = chunk;
-                        m.tiles_x = kgs::stream2d_tiles_x(x->geo.n);
+                        m.chunk = c.s2_tile ? c.s2_ty : chunk;
+                        m.tiles_x = c.s2_tile ? kgs::tile2d_tiles_x(x->geo.n, c.s2_tx)
+                                              : kgs::stream2d_tiles_x(x->geo.n);
                         // in/out/first are set by refresh_descriptors
                     }
-                    tb += kgs::stream2d_tasks(x->geo.n, chunk);
+                    tb += c.s2_tile ? kgs::tile2d_member_tiles(x->geo.n, c.s2_ty, c.s2_tx)
+                                    : kgs::stream2d_tasks(x->geo.n, chunk);
                 }
                 c.s2_tasks = tb;
             }

@@ -173,13 +173,24 @@ int64_t stream2d_tasks(int n, int chunk);
 hipError_t launch_stream2d(int precision, int stages, const Stream2dMember &one,
                            const Stream2dMember *list, int nm, int64_t total_tasks, hipStream_t s);
 
-// 2-D tiled kernel (kgs_tile2d.hip): `stages` (2 or 4) sweeps of one 2-D
-// grid per launch from `in` to `out`, tiles of ty rows x txc compressed
-// positions, each with its halo in LDS.
+// 2-D tiled kernel (kgs_tile2d.hip): `stages` (2 or 4) sweeps per launch
+// from `in` to `out`, tiles of ty rows x txc compressed positions, each with
+// its halo in LDS.  One grid (launch_tile2d), or many: a member list with
+// the Stream2dMember meaning of task_begin (first tile of the member, in
+// ascending order) and tiles_x = tile2d_tiles_x(n, txc), one workgroup per
+// tile; whether the launch starts the members' runs is `first_launch` for a
+// list and `one.first` otherwise.
+int tile2d_tiles_x(int n, int txc);
+int64_t tile2d_member_tiles(int n, int ty, int txc);
 int64_t tile2d_tiles(const Geometry &g, int ty, int txc);
+// Tile shape for one launch over grids of sizes n[0..count).
+void tile2d_group_shape(const int *n, int count, int &ty, int &txc);
 bool tile2d_shape_ok(const Geometry &g, int ty, int txc, int stages, int elem_bytes);
 hipError_t launch_tile2d(const Geometry &g, int precision, int stages, int ty, int txc,
                          const void *in, void *out, bool first, const Coef &k, hipStream_t s);
+hipError_t launch_tile2d_list(int precision, int stages, int ty, int txc, const Stream2dMember &one,
+                              const Stream2dMember *list, int nm, int64_t total_tiles,
+                              hipStream_t s, int first_launch = 0);
 // Writes the double-double sum of the energy density (without h^dim) to
 // out[0] + out[1] (device memory); `partials` holds 2*energy_partial_slots()
 // doubles.

@@ -26,6 +26,21 @@ using Pair = typename PairOf<T>::type;
 
 enum PairKind { PAIR_PQ = 0, PAIR_UV = 1 };
 
+// The state always lives in device (global) memory.  A state pointer read
+// from a descriptor in memory, rather than passed as a kernel argument,
+// carries no address space, and accesses through it would compile to FLAT
+// instructions, which also count against the LDS wait counter.  Every
+// state access below therefore goes through a pointer typed in the global
+// address space, which makes the compiler emit global loads and stores.
+template <typename T>
+using Global = __attribute__((address_space(1))) T;
+
+template <typename T>
+__device__ __forceinline__ T ld_global(const T *p)
+{
+    return *(const Global<T> *)p;
+}
+
 // First element of pair plane `pk` (PAIR_PQ or PAIR_UV) of colour c.
 template <typename T>
 __device__ __forceinline__ T *pair_plane(T *base, int64_t stride, int c, int pk)
@@ -42,7 +57,7 @@ __device__ __forceinline__ const T *pair_plane(const T *base, int64_t stride, in
 template <typename T>
 __device__ __forceinline__ Pair<T> ld_pair(const T *plane, int64_t t)
 {
-    return *reinterpret_cast<const Pair<T> *>(plane + 2 * t);
+    return *(const Global<Pair<T>> *)(plane + 2 * t);
 }
 
 template <typename T>
@@ -51,14 +66,14 @@ __device__ __forceinline__ void st_pair(T *plane, int64_t t, T a, T b)
     Pair<T> v;
     v.x = a;
     v.y = b;
-    *reinterpret_cast<Pair<T> *>(plane + 2 * t) = v;
+    *(Global<Pair<T>> *)(plane + 2 * t) = v;
 }
 
 // The first value of a pair (P of a (P, Q) pair, U of a (U, V) pair) alone.
 template <typename T>
 __device__ __forceinline__ T ld_first(const T *plane, int64_t t)
 {
-    return plane[2 * t];
+    return ld_global(plane + 2 * t);
 }
 
 }  // namespace kgs

@@ -624,8 +624,10 @@ int run_small(kgs_server *s)
 
 // 2-D requests of one precision taking k >= 2 steps this round: launches of
 // 2 steps (and of 1 step where needed to keep their number even, so that
-// every request ends in its own buffer) of the 2-D streaming kernel over
-// all of them, then the closing red sweep as one batched sweep.
+// every request ends in its own buffer) over all of them, of the
+// y-streaming kernel, or of the tiled kernel when the group is too small for
+// long streaming chunks and every grid is below n = 2048, then the closing
+// red sweep as one batched sweep.
 int run_stream2d(kgs_server *s, int prec, int64_t k, const std::vector<Request *> &rs)
 {
     const int nm = static_cast<int>(rs.size());
@@ -636,6 +638,15 @@ int run_stream2d(kgs_server *s, int prec, int64_t k, const std::vector<Request *
         return t;
     };
     while (chunk > 8 && tasks(chunk) < 2048) chunk /= 2;
+    // tiles when the group is too small for long streaming chunks
+    bool tile = chunk < 32;
+    std::vector<int> ns(static_cast<size_t>(nm));
+    for (int i = 0; i < nm; ++i) {
+        ns[i] = rs[i]->sim->geo.n;
+        if (ns[i] >= 2048) tile = false;
+    }
+    int ty = 0, tx = 0;
+    kgs::tile2d_group_shape(ns.data(), nm, ty, tx);
     const size_t s2_bytes = align_up(3 * nm * sizeof(kgs::Stream2dMember), 256);
     const size_t bm_bytes = align_up(nm * sizeof(kgs::BatchMember), 256);
     int rc = KGS_OK;
@@ -656,11 +667,11 @@ int run_stream2d(kgs_server *s, int prec, int64_t k, const std::vector<Request *
             m.task_begin = tb;
             m.k = x->coef;
             m.n = x->geo.n;
-            m.chunk = chunk;
-            m.tiles_x = kgs::stream2d_tiles_x(x->geo.n);
+            m.chunk = tile ? ty : chunk;
+            m.tiles_x = tile ? kgs::tile2d_tiles_x(x->geo.n, tx) : kgs::stream2d_tiles_x(x->geo.n);
             m.first = v == 0 ? 1 : 0;
         }
-        tb += kgs::stream2d_tasks(x->geo.n, chunk);
+        tb += tile ? kgs::tile2d_member_tiles(x->geo.n, ty, tx) : kgs::stream2d_tasks(x->geo.n, chunk);
         std::memset(&bm[i], 0, sizeof(bm[i]));
         bm[i].state = x->state;
         bm[i].stride = x->geo.stride;
@@ -678,9 +689,12 @@ int run_stream2d(kgs_server *s, int prec, int64_t k, const std::vector<Request *
     const auto *dd = reinterpret_cast<const kgs::Stream2dMember *>(sl->d);
     kgs::Stream2dMember none;
     std::memset(&none, 0, sizeof(none));
-    for (size_t i = 0; i < stages.size() && e == hipSuccess; ++i)
-        e = kgs::launch_stream2d(prec, stages[i], none, dd + (i == 0 ? 0 : (i % 2 ? 2 * nm : nm)), nm,
-                                 tb, st);
+    for (size_t i = 0; i < stages.size() && e == hipSuccess; ++i) {
+        const kgs::Stream2dMember *list = dd + (i == 0 ? 0 : (i % 2 ? 2 * nm : nm));
+        e = tile ? kgs::launch_tile2d_list(prec, stages[i], ty, tx, none, list, nm, tb, st,
+                                           i == 0 ? 1 : 0)
+                 : kgs::launch_stream2d(prec, stages[i], none, list, nm, tb, st);
+    }
     if (e == hipSuccess && blocks > 0x7fffffff) e = hipErrorInvalidValue;
     if (e == hipSuccess)
         e = kgs::launch_batch_sweep(2, prec, reinterpret_cast<const kgs::BatchMember *>(sl->d + s2_bytes),
@@ -690,7 +704,7 @@ int run_stream2d(kgs_server *s, int prec, int64_t k, const std::vector<Request *
     if (e != hipSuccess)
         for (Request *q : rs) {
             q->status = status_of(e);
-            q->err = std::string("2-D streaming launch: ") + hipGetErrorName(e);
+            q->err = std::string("2-D tiled/streaming launch: ") + hipGetErrorName(e);
         }
     return KGS_OK;
 }

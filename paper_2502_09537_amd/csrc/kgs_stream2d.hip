@@ -155,9 +155,12 @@ stream2d_kernel(Stream2dMember one, const Stream2dMember *__restrict__ list, int
                 int64_t total_tasks)
 {
     static_assert((S + 1) / 2 <= kHalo, "halo too narrow for S sweeps");
-    const int64_t task = static_cast<int64_t>(blockIdx.x) * kWaves + (threadIdx.x >> 6);
+    // the task is uniform across its wave: the member lookup and the
+    // descriptor stay in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int64_t task = static_cast<int64_t>(blockIdx.x) * kWaves + wave;
     if (task >= total_tasks) return;  // whole waves leave; nothing waits for them
-    const Stream2dMember *m = &one;
+    Stream2dMember mb = one;
     if (list) {
         int lo = 0, hi = nm - 1;
         while (lo < hi) {
@@ -165,15 +168,15 @@ stream2d_kernel(Stream2dMember one, const Stream2dMember *__restrict__ list, int
             if (list[mid].task_begin <= task) lo = mid;
             else hi = mid - 1;
         }
-        m = &list[lo];
+        mb = list[lo];
     }
     Task t;
-    t.n = m->n;
+    t.n = mb.n;
     t.H = t.n >> 1;
     t.lane = threadIdx.x & 63;
-    const int64_t local = task - m->task_begin;
-    const int tile = static_cast<int>(local % m->tiles_x);
-    const int chunk_i = static_cast<int>(local / m->tiles_x);
+    const int64_t local = task - mb.task_begin;
+    const int tile = static_cast<int>(local % mb.tiles_x);
+    const int chunk_i = static_cast<int>(local / mb.tiles_x);
     if (t.H <= 64) {
         // the whole periodic row in one wave, lanes >= H duplicate lanes - H
         t.xh = t.lane % t.H;
@@ -187,13 +190,13 @@ stream2d_kernel(Stream2dMember one, const Stream2dMember *__restrict__ list, int
         t.src_p = t.lane < 63 ? t.lane + 1 : 63;  // their results are not used
         t.in_tile = t.lane >= kHalo && t.lane < 64 - kHalo && xu < t.H;
     }
-    t.y0 = chunk_i * m->chunk;
-    t.L = min(m->chunk, t.n - t.y0);
-    const T *in = static_cast<const T *>(m->in);
-    T *out = static_cast<T *>(m->out);
-    const int64_t stride = m->stride;
-    const Coef k = m->k;
-    const bool first = m->first != 0;
+    t.y0 = chunk_i * mb.chunk;
+    t.L = min(mb.chunk, t.n - t.y0);
+    const T *in = static_cast<const T *>(mb.in);
+    T *out = static_cast<T *>(mb.out);
+    const int64_t stride = mb.stride;
+    const Coef k = mb.k;
+    const bool first = mb.first != 0;
 
     Pipe<T, S> st;
     {

@@ -14,7 +14,7 @@ namespace sweep_detail {
 template <typename T>
 __device__ __forceinline__ double ld(const T *p)
 {
-    return static_cast<double>(*p);
+    return static_cast<double>(ld_global(p));
 }
 
 // Index sum of the non-x coordinates of a row, and the rows one step away

@@ -82,17 +82,37 @@ __device__ __forceinline__ void tile_sweep(T *lds, int NB, const Coef &k, Owned<
     }
 }
 
+// Workgroup b runs tile b - task_begin of the member whose task_begin is the
+// largest one <= b (the member `one` when list is null); the member
+// descriptor gives its buffers, constants, n and tiles per row.  FIRST: this
+// launch starts every member's run (the first red sweep is the base pass).
 template <typename T, int S, int PPT, bool FIRST>
 __global__ void __launch_bounds__(kThreads)
-tile2d_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t stride, int n, int tiles_x,
-              int ty, int txc, Coef k)
+tile2d_kernel(Stream2dMember one, const Stream2dMember *__restrict__ list, int nm, int ty,
+              int txc)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *lds = reinterpret_cast<T *>(lds_raw);
     constexpr int HY = S, HX = (S + 1) / 2;
+    const int64_t task = blockIdx.x;
+    Stream2dMember mb = one;  // a copy: uniform values stay in scalar registers
+    if (list) {
+        int lo = 0, hi = nm - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (list[mid].task_begin <= task) lo = mid;
+            else hi = mid - 1;
+        }
+        mb = list[lo];
+    }
+    const T *__restrict__ in = static_cast<const T *>(mb.in);
+    T *__restrict__ out = static_cast<T *>(mb.out);
+    const int64_t stride = mb.stride;
+    const int n = mb.n, tiles_x = mb.tiles_x;
+    const Coef k = mb.k;
     const int H = n >> 1;
     const int BY = ty + 2 * HY, BX = txc + 2 * HX, NB = BY * BX;
-    const int tile = blockIdx.x;
+    const int tile = static_cast<int>(task - mb.task_begin);
     const int x0 = (tile % tiles_x) * txc, y0 = (tile / tiles_x) * ty;
 
     Owned<T, PPT> w;
@@ -164,51 +184,70 @@ tile2d_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t stride, int
 }
 
 template <typename T, int S, int PPT>
-hipError_t launch_ppt(const Geometry &g, int ty, int txc, const T *in, T *out, bool first,
-                      const Coef &k, hipStream_t s)
+hipError_t launch_ppt(int ty, int txc, bool first, const Stream2dMember &one,
+                      const Stream2dMember *list, int nm, int64_t tiles, hipStream_t s)
 {
     constexpr int HY = S, HX = (S + 1) / 2;
     const int NB = (ty + 2 * HY) * (txc + 2 * HX);
-    const int tiles_x = (g.half + txc - 1) / txc;
-    const int64_t tiles = static_cast<int64_t>(tiles_x) * ((g.n + ty - 1) / ty);
     const size_t lds = static_cast<size_t>(6) * NB * sizeof(T);
     auto kern = first ? tile2d_kernel<T, S, PPT, true> : tile2d_kernel<T, S, PPT, false>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(lds));
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(tiles)), dim3(kThreads), lds, s, in, out,
-                       g.stride, g.n, tiles_x, ty, txc, k);
+    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(tiles)), dim3(kThreads), lds, s, one, list,
+                       nm, ty, txc);
     return hipGetLastError();
 }
 
 template <typename T, int S>
-hipError_t launch_typed(const Geometry &g, int ty, int txc, const T *in, T *out, bool first,
-                        const Coef &k, hipStream_t s)
+hipError_t launch_typed(int ty, int txc, bool first, const Stream2dMember &one,
+                        const Stream2dMember *list, int nm, int64_t tiles, hipStream_t s)
 {
     const int NB = (ty + 2 * S) * (txc + 2 * ((S + 1) / 2));
-    if (NB <= 2 * kThreads) return launch_ppt<T, S, 2>(g, ty, txc, in, out, first, k, s);
-    if (NB <= 4 * kThreads) return launch_ppt<T, S, 4>(g, ty, txc, in, out, first, k, s);
-    return launch_ppt<T, S, 8>(g, ty, txc, in, out, first, k, s);
+    if (NB <= 2 * kThreads) return launch_ppt<T, S, 2>(ty, txc, first, one, list, nm, tiles, s);
+    if (NB <= 4 * kThreads) return launch_ppt<T, S, 4>(ty, txc, first, one, list, nm, tiles, s);
+    return launch_ppt<T, S, 8>(ty, txc, first, one, list, nm, tiles, s);
+}
+
+bool block_fits(int ty, int txc, int stages, int elem_bytes)
+{
+    if ((stages != 2 && stages != 4) || ty < 1 || txc < 1 || ty > 4096 || txc > 4096) return false;
+    const int NB = (ty + 2 * stages) * (txc + 2 * ((stages + 1) / 2));
+    return NB <= 8 * kThreads && static_cast<size_t>(6) * NB * elem_bytes <= 160 * 1024;
 }
 
 }  // namespace
 
-int64_t tile2d_tiles(const Geometry &g, int ty, int txc)
+int tile2d_tiles_x(int n, int txc) { return txc < 1 ? 0 : (n / 2 + txc - 1) / txc; }
+
+int64_t tile2d_member_tiles(int n, int ty, int txc)
 {
-    if (ty < 1 || txc < 1) return 0;
-    return static_cast<int64_t>((g.half + txc - 1) / txc) * ((g.n + ty - 1) / ty);
+    if (n < 2 || (n & 1) || ty < 1 || txc < 1) return 0;
+    return static_cast<int64_t>(tile2d_tiles_x(n, txc)) * ((n + ty - 1) / ty);
+}
+
+int64_t tile2d_tiles(const Geometry &g, int ty, int txc) { return tile2d_member_tiles(g.n, ty, txc); }
+
+void tile2d_group_shape(const int *n, int count, int &ty, int &txc)
+{
+    // the largest tile that still gives about four workgroups per CU of
+    // MI355X (larger tiles recompute less halo)
+    static const int shapes[][2] = {{16, 32}, {16, 16}, {8, 16}, {8, 8}};
+    for (const auto &sh : shapes) {
+        int64_t tiles = 0;
+        for (int i = 0; i < count; ++i) tiles += tile2d_member_tiles(n[i], sh[0], sh[1]);
+        ty = sh[0];
+        txc = sh[1];
+        if (tiles >= 1024) return;
+    }
 }
 
 bool tile2d_shape_ok(const Geometry &g, int ty, int txc, int stages, int elem_bytes)
 {
     if (g.dim != 2 || g.n < 2 || (g.n & 1) || g.count != static_cast<int64_t>(g.n) * (g.n / 2))
         return false;
-    if ((stages != 2 && stages != 4) || ty < 1 || txc < 1) return false;
-    const int NB = (ty + 2 * stages) * (txc + 2 * ((stages + 1) / 2));
-    if (NB > 8 * kThreads) return false;
-    if (static_cast<size_t>(6) * NB * elem_bytes > 160 * 1024) return false;
-    return tile2d_tiles(g, ty, txc) <= 0x7fffffff;
+    return block_fits(ty, txc, stages, elem_bytes) && tile2d_tiles(g, ty, txc) <= 0x7fffffff;
 }
 
 hipError_t launch_tile2d(const Geometry &g, int precision, int stages, int ty, int txc,
@@ -217,16 +256,40 @@ hipError_t launch_tile2d(const Geometry &g, int precision, int stages, int ty, i
     const int eb = precision == 0 ? 8 : 4;
     if (!in || !out || in == out || !tile2d_shape_ok(g, ty, txc, stages, eb))
         return hipErrorInvalidValue;
-    if (precision == 0) {
-        const double *i = static_cast<const double *>(in);
-        double *o = static_cast<double *>(out);
-        return stages == 2 ? launch_typed<double, 2>(g, ty, txc, i, o, first, k, s)
-                           : launch_typed<double, 4>(g, ty, txc, i, o, first, k, s);
-    }
-    const float *i = static_cast<const float *>(in);
-    float *o = static_cast<float *>(out);
-    return stages == 2 ? launch_typed<float, 2>(g, ty, txc, i, o, first, k, s)
-                       : launch_typed<float, 4>(g, ty, txc, i, o, first, k, s);
+    Stream2dMember m;
+    m.in = in;
+    m.out = out;
+    m.stride = g.stride;
+    m.task_begin = 0;
+    m.k = k;
+    m.n = g.n;
+    m.chunk = ty;
+    m.tiles_x = tile2d_tiles_x(g.n, txc);
+    m.first = first ? 1 : 0;
+    return launch_tile2d_list(precision, stages, ty, txc, m, nullptr, 1, tile2d_tiles(g, ty, txc),
+                              s);
+}
+
+hipError_t launch_tile2d_list(int precision, int stages, int ty, int txc, const Stream2dMember &one,
+                              const Stream2dMember *list, int nm, int64_t total_tiles,
+                              hipStream_t s, int first_launch)
+{
+    // every member of a launch is at the same point of its run: the first
+    // launch of a run (the descriptors' `first`) is a template choice
+    const bool first = list ? first_launch != 0 : one.first != 0;
+    const int eb = precision == 0 ? 8 : 4;
+    if (!block_fits(ty, txc, stages, eb) || nm < 1 || (!list && nm != 1) || total_tiles < 1 ||
+        total_tiles > 0x7fffffff)
+        return hipErrorInvalidValue;
+    if (!list && (one.in == nullptr || one.out == nullptr || one.in == one.out || one.n < 2 ||
+                  (one.n & 1) || one.task_begin != 0 || one.tiles_x != tile2d_tiles_x(one.n, txc) ||
+                  total_tiles != tile2d_member_tiles(one.n, ty, txc)))
+        return hipErrorInvalidValue;
+    if (precision == 0)
+        return stages == 2 ? launch_typed<double, 2>(ty, txc, first, one, list, nm, total_tiles, s)
+                           : launch_typed<double, 4>(ty, txc, first, one, list, nm, total_tiles, s);
+    return stages == 2 ? launch_typed<float, 2>(ty, txc, first, one, list, nm, total_tiles, s)
+                       : launch_typed<float, 4>(ty, txc, first, one, list, nm, total_tiles, s);
 }
 
 }  // namespace kgs

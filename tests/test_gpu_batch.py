@@ -154,10 +154,12 @@ def test_batch_rejects_bad_input():
 
 @pytest.mark.parametrize("graph", [False, True])
 @pytest.mark.parametrize("prec", [workloads.FP64, workloads.FP32])
-def test_2d_batches_stream_and_equal_individual_runs(graph, prec):
-    # uneven 2-D members beyond one workgroup: uniform runs use the 2-D
-    # streaming kernel (2 steps per launch, an even number of launches)
-    sizes = [130, 200, 256, 1030, 66 * 2, 90 * 2]
+@pytest.mark.parametrize("sizes", [[130, 200, 256, 1030, 66 * 2, 90 * 2], [2048, 130, 514]],
+                         ids=["tiled", "streamed"])
+def test_2d_batches_stream_and_equal_individual_runs(graph, prec, sizes):
+    # uneven 2-D members beyond one workgroup: uniform runs use 2 steps per
+    # launch (an even number of launches) of the tiled kernel when every
+    # member is below n = 2048, else of the y-streaming kernel
     probs = [workloads.random_problem(2, n, seed=500 + n, tau=0.02, amp=0.5, precision=prec)
              for n in sizes]
     say("2-D batch streaming, graph =", graph, "prec", prec)

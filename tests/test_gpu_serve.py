@@ -62,6 +62,28 @@ def test_results_in_the_mix_equal_results_alone():
     srv.close()
 
 
+@pytest.mark.parametrize("sizes", [[130, 514], [2048, 130]], ids=["tiled", "streamed"])
+def test_2d_groups_equal_results_alone(sizes):
+    # 2-D requests advanced together: tiled launches when every grid is
+    # below n = 2048, y-streaming launches otherwise
+    probs = [workloads.gaussian_problem(2, n, 40 + i, -6.0, 6.0, 0.01, 5 + i, precision=i % 2)
+             for i, n in enumerate(sizes)]
+    say("2-D groups", sizes)
+    srv = kgs.Server(budget_bytes=8 << 30, steps_per_round=4)
+    ids = [srv.submit_problem(p) for p in probs]
+    while True:
+        nr, nq = srv.run(1)
+        if nr == 0 and nq == 0:
+            break
+    for rid, p in zip(ids, probs):
+        info = srv.poll(rid)
+        assert info.state == kgs.KGS_REQ_DONE, (rid, info.state, info.status)
+        ref, e_ref = alone(p, p.steps)
+        assert equal(srv.result(rid), ref), p.n
+        assert info.energy_end == e_ref
+    srv.close()
+
+
 def test_admission_respects_the_budget():
     probs = [workloads.gaussian_problem(2, 128, i, -6.0, 6.0, 0.01, 12) for i in range(6)]
     say("budget")
