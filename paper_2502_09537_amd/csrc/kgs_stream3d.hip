@@ -20,7 +20,8 @@
 // and l_p - 2 - j of level j) in the registers of the same thread: a
 // three-plane FIFO per level.  In-plane neighbours come from the other
 // threads through LDS, published at the end of the previous step
-// (double-buffered, one barrier per step).  The neighbour sums use the same
+// (double-buffered, one barrier per step) as (P, Q) pairs and U, so that a
+// neighbour costs two LDS reads.  The neighbour sums use the same
 // order as the one-sweep kernel (axis 0 -, +, axis 1 -, +, axis 2 -, +), so
 // both kernels give bitwise the same state.
 #include <hip/hip_runtime.h>
@@ -88,6 +89,11 @@ __device__ __forceinline__ int wrap(int v, int m)
 // read, falls in distinct banks.
 __host__ __device__ constexpr int lds_pitch(int bx) { return bx | 1; }
 
+// Slots of one published plane, even so that every (P, Q) pair array starts
+// on a pair boundary.  A level's publication is NL (P, Q) pairs followed by
+// NL values of U.
+__host__ __device__ constexpr int lds_plane(int bx, int by) { return (lds_pitch(bx) * by + 1) & ~1; }
+
 // Largest workgroup per instantiation: the four-sweep pipeline keeps 16
 // planes of FIFO per thread and needs more than 128 VGPRs, so at most 3
 // waves per SIMD (12 per workgroup); a compiled-in tile has exactly its
@@ -114,7 +120,7 @@ struct Pipe {
 // Thread geometry shared by all steps of a workgroup.
 struct Geo {
     int NT;              // threads with a column of the block
-    int NL;              // LDS slots per published plane (odd row pitch)
+    int NL;              // LDS slots per published plane (odd row pitch, even total)
     int wave;            // first thread of this thread's wave
     int need[5];         // stage j runs on threads below need[S - 1 - j]
     bool live, in_tile;  // has a column / writes its column
@@ -180,7 +186,7 @@ __device__ __forceinline__ void pipeline_step(Pipe<T, S> &st, const Geo &g, T *l
                                               int steps, int &z_load, const Coef &k)
 {
     constexpr int HX = (S + 1) / 2, HY = S;
-    const int NL = TX ? lds_pitch(TX + 2 * HX) * (TY + 2 * HY) : g.NL;
+    const int NL = TX ? lds_plane(TX + 2 * HX, TY + 2 * HY) : g.NL;
     constexpr int s0 = PH % 3, s1 = (PH + 2) % 3, s2 = (PH + 1) % 3;  // steps p, p-1, p-2
     // the blue plane of step p arrived in Bn; fetch step p + 1 (red plane
     // into the slot of step p - 2, which no stage reads any more)
@@ -204,18 +210,33 @@ __device__ __forceinline__ void pipeline_step(Pipe<T, S> &st, const Geo &g, T *l
         // level-j neighbours: z -/+ 1 from registers, in-plane from LDS
         const Vals<T> &up = (j == 0) ? st.B[s0] : st.F[j > 0 ? j - 1 : 0][s0];
         const Vals<T> &dn = (j == 0) ? st.B[s2] : st.F[j > 0 ? j - 1 : 0][s2];
-        const T *pl0 = pub + j * 3 * NL;
+        // level-j publication: (P, Q) pairs, then U
+        const Pair<T> *ppq = reinterpret_cast<const Pair<T> *>(pub + j * 3 * NL);
+        const T *pu = pub + j * 3 * NL + 2 * NL;
         double sum[3];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            const T *pl = pl0 + q * NL;
-            double a = static_cast<double>(dn.f[q]);
-            a = a + static_cast<double>(up.f[q]);
-            a = a + static_cast<double>(pl[g.i_ym]);
-            a = a + static_cast<double>(pl[g.i_yp]);
-            a = a + static_cast<double>(pl[i_xm]);
-            a = a + static_cast<double>(pl[i_xp]);
-            sum[q] = a;
+        {
+            const Pair<T> n0 = ppq[g.i_ym], n1 = ppq[g.i_yp], n2 = ppq[i_xm], n3 = ppq[i_xp];
+            double a = static_cast<double>(dn.f[0]);
+            a = a + static_cast<double>(up.f[0]);
+            a = a + static_cast<double>(n0.x);
+            a = a + static_cast<double>(n1.x);
+            a = a + static_cast<double>(n2.x);
+            a = a + static_cast<double>(n3.x);
+            sum[0] = a;
+            double b = static_cast<double>(dn.f[1]);
+            b = b + static_cast<double>(up.f[1]);
+            b = b + static_cast<double>(n0.y);
+            b = b + static_cast<double>(n1.y);
+            b = b + static_cast<double>(n2.y);
+            b = b + static_cast<double>(n3.y);
+            sum[1] = b;
+            double c = static_cast<double>(dn.f[2]);
+            c = c + static_cast<double>(up.f[2]);
+            c = c + static_cast<double>(pu[g.i_ym]);
+            c = c + static_cast<double>(pu[g.i_yp]);
+            c = c + static_cast<double>(pu[i_xm]);
+            c = c + static_cast<double>(pu[i_xp]);
+            sum[2] = c;
         }
         // own values at level j: the last output of this colour
         const Vals<T> &own = (j == 0) ? st.R[s1] : (j == 1) ? st.B[s2] : st.F[j > 1 ? j - 2 : 0][s2];
@@ -248,13 +269,16 @@ __device__ __forceinline__ void pipeline_step(Pipe<T, S> &st, const Geo &g, T *l
     // publish the newest plane of every level that a stage reads next step
     if (g.live) {
         T *pw = lds + static_cast<size_t>(p & 1) * S * 3 * NL;
+        auto publish = [&](int j, const Vals<T> &x) {
+            Pair<T> pq;
+            pq.x = x.f[0];
+            pq.y = x.f[1];
+            reinterpret_cast<Pair<T> *>(pw + j * 3 * NL)[g.i_self] = pq;
+            pw[j * 3 * NL + 2 * NL + g.i_self] = x.f[2];
+        };
+        publish(0, st.B[s0]);
 #pragma unroll
-        for (int q = 0; q < 3; ++q) pw[q * NL + g.i_self] = st.B[s0].f[q];
-#pragma unroll
-        for (int j = 1; j < S; ++j) {
-#pragma unroll
-            for (int q = 0; q < 3; ++q) pw[(j * 3 + q) * NL + g.i_self] = st.F[j - 1][s0].f[q];
-        }
+        for (int j = 1; j < S; ++j) publish(j, st.F[j - 1][s0]);
     }
     __syncthreads();
 }
@@ -279,7 +303,7 @@ stream3d_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t stride, i
     const int PX = lds_pitch(BX);
     Geo g;
     g.NT = BX * BY;
-    g.NL = PX * BY;
+    g.NL = lds_plane(BX, BY);
     const int tid = threadIdx.x;
     g.live = tid < g.NT;
     g.wave = tid & ~63;
@@ -358,7 +382,7 @@ hipError_t launch_typed(const Geometry &g, const StreamShape &sh, const T *in, T
     const int H = g.n / 2;
     const int BX = sh.tile_x + 2 * HX, BY = sh.tile_y + 2 * HY;
     const int NT = BX * BY;
-    const int NL = lds_pitch(BX) * BY;
+    const int NL = lds_plane(BX, BY);
     const int threads = (NT + 63) / 64 * 64;
     const int tiles_x = (H + sh.tile_x - 1) / sh.tile_x;
     const int tiles_y = (g.n + sh.tile_y - 1) / sh.tile_y;
@@ -400,7 +424,7 @@ bool stream3d_shape_ok(const Geometry &g, const StreamShape &sh, int elem_bytes)
     const int NT = BX * BY;
     const int limit = S == 4 ? max_threads<float, 4>() : max_threads<float, 2>();
     if ((NT + 63) / 64 * 64 > limit) return false;
-    return static_cast<size_t>(2) * S * 3 * lds_pitch(BX) * BY * elem_bytes <= 160 * 1024;
+    return static_cast<size_t>(2) * S * 3 * lds_plane(BX, BY) * elem_bytes <= 160 * 1024;
 }
 
 hipError_t launch_stream3d(const Geometry &g, int precision, const StreamShape &sh, int stages,
