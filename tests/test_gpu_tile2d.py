@@ -102,3 +102,23 @@ def test_tile2d_rejects_bad_shapes():
         with pytest.raises(kgs.KgsError):
             sim.tuning = tuning(kgs.KGS_KERNEL_TILE, 4, 4, 1)
         sim.close()
+
+
+def test_autotune_2d_keeps_state_and_results():
+    # the 2-D candidates (sweeps, y-streaming chunks, tiles) all give the
+    # same state; tuning leaves the state as it was
+    p = workloads.random_problem(2, 200, seed=9, tau=0.02, amp=0.5)
+    say("2-D autotune")
+    sim = kgs.simulation_from_problem(p)
+    before = sim.read_state()
+    best = sim.autotune(steps=2, use_cache=False)
+    for x, y in zip(before, sim.read_state()):
+        assert np.array_equal(x, y)
+    assert best.kernel in (kgs.KGS_KERNEL_SWEEP, kgs.KGS_KERNEL_STREAM, kgs.KGS_KERNEL_TILE)
+    assert sim.tuning.kernel == best.kernel
+    sim.step(3)
+    tuned = sim.read_state()
+    sim.close()
+    (ref, _) = run(p, [3], tuning(kgs.KGS_KERNEL_SWEEP))
+    for x, y in zip(tuned, ref):
+        assert np.array_equal(x, y)
