@@ -175,8 +175,9 @@ int kgs_get_tuning(const kgs_sim *sim, kgs_tuning *out);
 int kgs_set_tuning(kgs_sim *sim, const kgs_tuning *t);
 
 /* Autotuner: time each candidate launch configuration that fits the grid
- * (sweep block sizes; for 3-D grids also streaming tile/chunk shapes with 1
- * or 2 steps per launch) over `steps` DP-AVF2 steps on the handle's current
+ * (sweep block sizes; for 3-D grids also streaming tile/chunk shapes, for
+ * 2-D grids streaming chunks and tiles, with 1 or 2 steps per launch) over
+ * `steps` DP-AVF2 steps on the handle's current
  * state, restore the state after every candidate, and keep the fastest.  The
  * state is unchanged on return.  With use_cache != 0 a winner found earlier
  * in this process for the same (dim, n, precision, device) is reused without
@@ -201,9 +202,12 @@ int64_t kgs_required_bytes(const kgs_config *cfg);
 
 /* ------------------------------------------------------------------------
  * Batches: many independent simulations (any dimensions, sizes, parameters
- * and precisions) advanced together.  Each colour sweep is one launch per
- * (dimension, precision) class over all members instead of one launch per
- * simulation; a uniform run can be captured once in a hipGraph and replayed.
+ * and precisions) advanced together, one launch per (dimension, precision)
+ * class over all members instead of one launch per simulation: members that
+ * fit one workgroup run a whole call in one persistent launch; 2-D members
+ * run 2 steps per launch (y-streaming or tiled kernel) in uniform runs of 2
+ * or more steps; every other run is one launch per colour sweep.  A uniform
+ * run can be captured once in a hipGraph and replayed.
  * Every member ends bitwise where kgs_step would have left it (points of one
  * colour are independent, sec. 4.2, so the launch layout does not matter).
  * ---------------------------------------------------------------------- */
@@ -241,8 +245,9 @@ const char *kgs_batch_last_error(const kgs_batch *b);
  * start together in one persistent resident launch per round and run all
  * their steps; all other grids advance in rounds of up to steps_per_round
  * steps, the requests with the least remaining work first, up to round_work
- * point-steps per round (3-D float64 grids with their own streaming kernel,
- * the rest in one batched launch sequence).  A request that arrives while
+ * point-steps per round (3-D grids of n >= 96 with their own streaming
+ * kernel, 2-D grids advanced together 2 steps per launch, the rest in one
+ * batched launch sequence).  A request that arrives while
  * others run joins at the next round.  Finished requests are retired to host
  * memory and their device memory returns to the server's pool.  Host code
  * does not wait for the GPU between rounds, except to keep at most two
