@@ -147,7 +147,7 @@ enum {
                                 e.g. 1-D n <= 6826 float64 / 8192 float32):
                                 the whole grid in one workgroup's LDS and
                                 registers, all steps of a call in one launch */
-    KGS_KERNEL_TILE = 4,   /* 2-D: 2 or 4 colour sweeps per launch between two
+    KGS_KERNEL_TILE = 4,   /* 2-D: 2, 4 or 8 colour sweeps per launch between two
                               state buffers, each workgroup running them on a
                               tile_y x tile_x tile (rows x points of one
                               colour) plus a halo held in LDS              */
@@ -164,8 +164,10 @@ typedef struct {
                               1); KGS_KERNEL_TILE: rows (axis 0)           */
     int32_t chunk;         /* KGS_KERNEL_STREAM: planes (3-D) or rows (2-D) of
                               axis 0 per workgroup (3-D) or wave (2-D)        */
-    int32_t steps_per_launch; /* KGS_KERNEL_STREAM, KGS_KERNEL_TILE: 1 or 2
-                              DP-AVF2 steps (2 or 4 colour sweeps) per launch */
+    int32_t steps_per_launch; /* KGS_KERNEL_STREAM: 1 or 2 DP-AVF2 steps (2 or
+                              4 colour sweeps) per launch; KGS_KERNEL_TILE:
+                              1, 2 or 4 (the last launches of a call take
+                              the remaining steps, 2 or 1 at a time)        */
     int32_t reserved[2];   /* must be 0                                       */
 } kgs_tuning;
 

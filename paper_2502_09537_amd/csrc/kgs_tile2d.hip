@@ -1,6 +1,7 @@
-// 2-D tiled kernel: S consecutive colour sweeps (S/2 DP-AVF2 steps) of a 2-D
-// grid in one launch, each workgroup holding one tile of the grid plus a halo
-// in LDS, reading the state from one buffer and writing it to another.
+// 2-D tiled kernel: S = 2, 4 or 8 consecutive colour sweeps (S/2 DP-AVF2
+// steps) of a 2-D grid in one launch, each workgroup holding one tile of the
+// grid plus a halo in LDS, reading the state from one buffer and writing it
+// to another.
 //
 // Why: a 2-D grid of moderate size (1024^2 is 0.5 M points per colour) has
 // too few rows for the y-streaming kernel to give every SIMD more than about
@@ -212,7 +213,8 @@ hipError_t launch_typed(int ty, int txc, bool first, const Stream2dMember &one,
 
 bool block_fits(int ty, int txc, int stages, int elem_bytes)
 {
-    if ((stages != 2 && stages != 4) || ty < 1 || txc < 1 || ty > 4096 || txc > 4096) return false;
+    if ((stages != 2 && stages != 4 && stages != 8) || ty < 1 || txc < 1 || ty > 4096 || txc > 4096)
+        return false;
     const int NB = (ty + 2 * stages) * (txc + 2 * ((stages + 1) / 2));
     return NB <= 8 * kThreads && static_cast<size_t>(6) * NB * elem_bytes <= 160 * 1024;
 }
@@ -286,10 +288,12 @@ hipError_t launch_tile2d_list(int precision, int stages, int ty, int txc, const 
                   total_tiles != tile2d_member_tiles(one.n, ty, txc)))
         return hipErrorInvalidValue;
     if (precision == 0)
-        return stages == 2 ? launch_typed<double, 2>(ty, txc, first, one, list, nm, total_tiles, s)
-                           : launch_typed<double, 4>(ty, txc, first, one, list, nm, total_tiles, s);
-    return stages == 2 ? launch_typed<float, 2>(ty, txc, first, one, list, nm, total_tiles, s)
-                       : launch_typed<float, 4>(ty, txc, first, one, list, nm, total_tiles, s);
+        return stages == 2   ? launch_typed<double, 2>(ty, txc, first, one, list, nm, total_tiles, s)
+               : stages == 4 ? launch_typed<double, 4>(ty, txc, first, one, list, nm, total_tiles, s)
+                             : launch_typed<double, 8>(ty, txc, first, one, list, nm, total_tiles, s);
+    return stages == 2   ? launch_typed<float, 2>(ty, txc, first, one, list, nm, total_tiles, s)
+           : stages == 4 ? launch_typed<float, 4>(ty, txc, first, one, list, nm, total_tiles, s)
+                         : launch_typed<float, 8>(ty, txc, first, one, list, nm, total_tiles, s);
 }
 
 }  // namespace kgs

@@ -46,7 +46,8 @@ std::vector<kgs_tuning> candidates(const kgs_sim *s)
             }
         const int eb = s->cfg.precision == KGS_FP32 ? 4 : 8;
         const int tiles[][3] = {{8, 8, 2},   {8, 16, 2},  {16, 16, 2}, {16, 32, 2},
-                                {32, 16, 2}, {32, 32, 2}, {16, 16, 1}, {32, 32, 1}};
+                                {32, 16, 2}, {32, 32, 2}, {16, 16, 1}, {32, 32, 1},
+                                {16, 16, 4}, {16, 32, 4}, {32, 32, 4}};
         for (const auto &tl : tiles) {
             if (!kgs::tile2d_shape_ok(s->geo, tl[0], tl[1], 2 * tl[2], eb)) continue;
             kgs_tuning t;

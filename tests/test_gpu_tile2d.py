@@ -51,6 +51,12 @@ CASES = [
     (256, 40, 32, 2, [5]),      # 8 points per thread
     (256, 64, 32, 2, [2]),      # too many points for one workgroup: rejected
     (1024, 32, 16, 2, [3]),
+    # 4 steps (8 sweeps) per launch: 8 halo rows, 4 compressed positions
+    (2, 1, 1, 4, [6]),
+    (30, 7, 5, 4, [5]),         # one launch of 4 steps, then 1
+    (64, 16, 16, 4, [4, 3]),    # the tail of a call: 2 steps, then 1
+    (130, 32, 16, 4, [9]),
+    (256, 24, 24, 4, [8]),
 ]
 
 
