@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--round-work", type=int, default=0,
                     help="serving: point-steps per big-grid round (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=2,
+    ap.add_argument("--cpu-steps", type=int, default=6,
                     help="oracle steps on the full grid for the CPU baseline")
     return ap.parse_args()
 
