@@ -367,3 +367,28 @@ def test_soliton_accuracy_and_time_order_on_the_paper_grid():
     parts = np.array(errs) - floor
     orders = np.log2(parts[:-1] / parts[1:])
     assert np.all(orders > 1.8), (floor, errs, orders)
+
+
+def test_finite_speed_of_propagation_lets_sub_blocks_stand_in_for_the_grid():
+    """K steps are 2K+1 colour sweeps, and a sweep moves information one
+    point along each axis, so the oracle on a periodic sub-block that starts
+    from the same data agrees bitwise with the full-grid run wherever the
+    sub-block's wrong wrap-around cannot reach (the sampled full-size GPU
+    check relies on this); one point closer to the block edge it does
+    not."""
+    p = workloads.random_problem(3, 48, seed=3, tau=0.04, amp=0.5)
+    full = oracle.State.from_fields(p.psi, p.u, p.v)
+    oracle.step(oracle.Grid(3, 48, p.lo, p.hi, p.kappa1, p.kappa2, p.mu, p.gamma), p.tau,
+                full, 4)
+    h = (p.hi - p.lo) / p.n
+    for st in [(0, 0, 0), (40, 20, 46), (12, 30, 6)]:
+        idx = np.ix_(*[(np.arange(24) + s) % 48 for s in st])
+        sub = oracle.State.from_fields(p.psi[idx], p.u[idx], p.v[idx])
+        oracle.step(oracle.Grid(3, 24, 0.0, 24 * h, p.kappa1, p.kappa2, p.mu, p.gamma), p.tau,
+                    sub, 4)
+        safe = (slice(9, 15),) * 3  # at least 9 = 2*4+1 points from the block edge
+        for a, b in zip(sub.arrays(), full.arrays()):
+            assert np.array_equal(a[safe], b[idx][safe])
+        wide = (slice(8, 16),) * 3  # one point closer: the wrap has arrived
+        assert any(not np.array_equal(a[wide], b[idx][wide])
+                   for a, b in zip(sub.arrays(), full.arrays()))
