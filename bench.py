@@ -398,7 +398,7 @@ def bench_small_dims(args):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs one simulation on one GPU; --gpus must be 1"}))
         sys.exit(2)
     if args.workload == "batched":
         return bench_batched(args)
