@@ -439,7 +439,7 @@ def main():
             t.tile_x, t.tile_y, t.chunk, t.steps_per_launch = (int(v) for v in args.tile.split(","))
         sim.tuning = t
     if args.autotune:
-        sim.autotune(steps=4, use_cache=False)
+        sim.autotune(steps=16, use_cache=False)
     info = sim.info()
     tun = sim.tuning
     sim.step(args.warmup)

@@ -179,7 +179,7 @@ int kgs_set_tuning(kgs_sim *sim, const kgs_tuning *t);
 /* Autotuner: time each candidate launch configuration that fits the grid
  * (sweep block sizes; for 3-D grids also streaming tile/chunk shapes, for
  * 2-D grids streaming chunks and tiles, with 1 or 2 steps per launch) over
- * `steps` DP-AVF2 steps on the handle's current
+ * `steps` DP-AVF2 steps (the faster of two timings) on the handle's current
  * state, restore the state after every candidate, and keep the fastest.  The
  * state is unchanged on return.  With use_cache != 0 a winner found earlier
  * in this process for the same (dim, n, precision, device) is reused without

@@ -420,6 +420,8 @@ int sim_create_pooled(const kgs_config *cfg, const double *P, const double *Q, c
 
 int default_kernel(const kgs_config &cfg) { return default_tuning(cfg).kernel; }
 
+kgs_tuning default_tuning_of(const kgs_config &cfg) { return default_tuning(cfg); }
+
 int64_t state_bytes(const kgs_config &cfg)
 {
     return 8 * make_geometry(cfg).stride * static_cast<int64_t>(elem_bytes(cfg.precision));

@@ -44,6 +44,8 @@ int sim_create_pooled(const kgs_config *cfg, const double *P, const double *Q, c
 void sim_destroy_pooled(kgs_sim *s);
 // KGS_KERNEL_* that a new handle for cfg (valid) runs by default.
 int default_kernel(const kgs_config &cfg);
+// The library's launch configuration for cfg (what KGS_KERNEL_AUTO picks).
+kgs_tuning default_tuning_of(const kgs_config &cfg);
 // Give the handle its second state buffer (ping-pong kernels) if it has none.
 int sim_ensure_state2(kgs_sim *s);
 // Bytes of one state buffer (8 planes) of a valid cfg.

@@ -23,7 +23,8 @@ std::mutex g_cache_mutex;
 
 std::vector<kgs_tuning> candidates(const kgs_sim *s)
 {
-    std::vector<kgs_tuning> out;
+    // the library's own choice first, so that tuning never loses to it
+    std::vector<kgs_tuning> out{kgs::default_tuning_of(s->cfg)};
     auto sweep = [&](int block) {
         kgs_tuning t;
         std::memset(&t, 0, sizeof(t));
@@ -66,6 +67,7 @@ std::vector<kgs_tuning> candidates(const kgs_sim *s)
             {16, 16, 128, 2}, {16, 17, 64, 2}, {16, 16, 64, 2}, {12, 24, 128, 2}, {8, 32, 128, 2},
             {32, 16, 64, 2},  {32, 16, 128, 2}, {16, 40, 64, 2}, {32, 16, 64, 1}, {64, 8, 64, 1},
             {16, 32, 64, 1},  {32, 8, 32, 1},   {16, 16, 32, 2}, {32, 20, 64, 2},
+            {16, 16, 16, 2},  {16, 16, 8, 2},   {16, 16, 16, 1},
         };
         for (const auto &sh : shapes) {
             kgs::StreamShape ss = {sh[0], sh[1], sh[2], sh[3]};
@@ -118,18 +120,21 @@ extern "C" int kgs_autotune(kgs_sim *s, int32_t steps, int32_t use_cache, kgs_tu
     if (rc == KGS_OK) {
         for (const kgs_tuning &t : candidates(s)) {
             if (kgs_set_tuning(s, &t) != KGS_OK) continue;
-            // warm-up step, then `steps` timed steps; restore the state after
+            // a warm-up step, then the faster of two timed calls of `steps`
+            // steps (one short sample alone picked configurations that lose
+            // in longer runs); the state is restored after the candidate
             if (kgs_step(s, 1) != KGS_OK) break;
-            if (hipEventRecord(a, s->stream) != hipSuccess || kgs_step(s, steps) != KGS_OK ||
-                hipEventRecord(b, s->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
-                rc = KGS_EDEVICE;
-                break;
+            float ms = -1.0f;
+            for (int rep = 0; rep < 2 && rc == KGS_OK; ++rep) {
+                float m = 0.0f;
+                if (hipEventRecord(a, s->stream) != hipSuccess || kgs_step(s, steps) != KGS_OK ||
+                    hipEventRecord(b, s->stream) != hipSuccess ||
+                    hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&m, a, b) != hipSuccess)
+                    rc = KGS_EDEVICE;
+                else if (ms < 0.0f || m < ms)
+                    ms = m;
             }
-            float ms = 0.0f;
-            if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
-                rc = KGS_EDEVICE;
-                break;
-            }
+            if (rc != KGS_OK) break;
             if (best_ms < 0.0f || ms < best_ms) {
                 best_ms = ms;
                 winner = t;
