@@ -69,11 +69,4 @@ __device__ __forceinline__ void st_pair(T *plane, int64_t t, T a, T b)
     *(Global<Pair<T>> *)(plane + 2 * t) = v;
 }
 
-// The first value of a pair (P of a (P, Q) pair, U of a (U, V) pair) alone.
-template <typename T>
-__device__ __forceinline__ T ld_first(const T *plane, int64_t t)
-{
-    return ld_global(plane + 2 * t);
-}
-
 }  // namespace kgs
