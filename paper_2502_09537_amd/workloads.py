@@ -101,6 +101,23 @@ def config_3d(n: int = 256, steps: int = 200, precision: int = FP64) -> Problem:
     return p
 
 
+def accuracy_2d(level: int = 0, precision: int = FP64) -> Problem:
+    """The 2-D example of sec. 5.1 (the problem of Tab. conv2d): periodic on
+    [-10,10)^2, kappa1 = kappa2 = gamma = mu = 1,
+    psi0 = (1+i) e^{-(x^2+y^2)}, u0 = tanh(x^2+y^2),
+    v0 = sin(x+y) e^{-2(x^2+y^2)}, up to t = 1.  Level L halves h and tau L
+    times from (h, tau) = (5/16, 1/50): n = 64 * 2^L, 50 * 2^L steps."""
+    n, steps = 64 << level, 50 << level
+    p = Problem(f"accuracy2d_l{level}", 2, n, -10.0, 10.0, 1.0 / steps, steps,
+                precision=precision)
+    x, y = axes(2, n, p.lo, p.hi)
+    r2 = x ** 2 + y ** 2
+    p.psi = (1.0 + 1.0j) * np.exp(-r2)
+    p.u = np.tanh(r2)
+    p.v = np.sin(x + y) * np.exp(-2.0 * r2)
+    return p
+
+
 def random_problem(dim: int, n: int, seed: int, tau: float = 0.01, amp: float = 1.0,
                    precision: int = FP64, steps: int = 1, lo: float = -4.0, hi: float = 4.0,
                    params=None) -> Problem:

@@ -285,3 +285,18 @@ def test_nonfinite_energy_reported():
     rc = kgs.lib().kgs_energy(sim.handle, __import__("ctypes").byref(e))
     sim.close()
     assert rc == kgs.KGS_ENONFINITE and not np.isfinite(e.value)
+
+
+# ---------------------------------------------------------------------------
+# the 2-D example of sec. 5.1 at the three (h, tau) levels of Tab. conv2d
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("level", [0, 1, 2])
+def test_parity_accuracy_example_2d_fp64(level):
+    p = workloads.accuracy_2d(level)
+    assert_parity(p, p.steps, FP64_TOL)
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_parity_accuracy_example_2d_fp32(level):
+    p = workloads.accuracy_2d(level, precision=workloads.FP32)
+    assert_parity(p, p.steps, FP32_TOL)
