@@ -33,15 +33,18 @@ METRIC = "lattice-point updates/s + % HBM roofline (3D 256³ FP64); served p50/p
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["3d", "batched", "serving", "1d", "2d"], default="3d",
+    ap.add_argument("--workload", choices=["3d", "batched", "serving", "1d", "2d", "paper2d",
+                                           "paper3d"], default="3d",
                     help="3d: the headline line (default); batched: 64 uneven 2-D instances; "
-                         "serving: Poisson request stream; 1d/2d: the 1-D and 2-D configurations")
+                         "serving: Poisson request stream; 1d/2d: the 1-D and 2-D configurations; "
+                         "paper2d/paper3d: the paper's own GPU timing examples (t = 1, tau = 0.01)")
     ap.add_argument("--steps", type=int, default=None,
                     help="timed DP-AVF2 steps (default: the workload's own count)")
     # the GPU needs tens of milliseconds of load to reach its steady clock:
     # 200 steps of the 3-D grid take about 50 ms
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--n", type=int, default=None,
+                    help="points per axis (3d, paper3d: 256; paper2d: 2048)")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--kernel", choices=["auto", "sweep", "stream"], default="auto")
     ap.add_argument("--tile", type=str, default=None,
@@ -409,6 +412,88 @@ def bench_small_dims(args):
     print(json.dumps(out), flush=True)
 
 
+# The paper's GPU times (one NVIDIA A40, precision not stated, t = 1 with
+# tau = 0.01, i.e. 100 steps) for its timing examples: Tab. time-2d (2-D four
+# solitons) and Tab. gpu3d_list (3-D example of sec. 5.2), by points per axis.
+PAPER_A40_S = {
+    "paper2d": {512: 2.29e-2, 768: 5.25e-2, 1024: 9.34e-2, 1280: 1.28e-1, 1536: 1.96e-1,
+                1792: 2.76e-1, 2048: 3.70e-1},
+    "paper3d": {128: 1.72e-1, 192: 6.25e-1, 256: 1.61, 320: 3.30, 384: 6.03, 448: 9.96,
+                512: 15.6},
+}
+
+
+def bench_paper(args):
+    """One of the paper's own GPU timing examples at its own size and step
+    count: the run of 100 steps with the state resident on the GPU (value),
+    repeated, and the same run with the state copied from and back to host
+    memory around it (as the paper's GPU algorithm does), against the paper's
+    A40 time for the same grid."""
+    import torch
+
+    from paper_2502_09537_amd import kgs, workloads
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    prec = workloads.FP32 if args.precision == "fp32" else workloads.FP64
+    n = args.n or (2048 if args.workload == "paper2d" else 256)
+    p = (workloads.timing_2d if args.workload == "paper2d" else workloads.timing_3d)(n, prec)
+    steps = args.steps if args.steps is not None else p.steps
+    sim = kgs.simulation_from_problem(p)
+    info = sim.info()
+    sim.step(args.warmup)
+    sim.sync()
+    e0 = sim.energy()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    wall = time.perf_counter() - t0
+    e1 = sim.energy()
+    reps = []
+    for _ in range(args.repeats):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        sim.step(steps)
+        b.record(stream)
+        torch.cuda.synchronize()
+        reps.append(a.elapsed_time(b) / 1e3)
+    sim.close()
+
+    def host_run():
+        t = time.perf_counter()
+        s = kgs.simulation_from_problem(p, host=True)
+        s.step(steps)
+        s.read_state()
+        s.close()
+        return time.perf_counter() - t
+    host_run()
+    host_s = host_run()
+
+    names = {kgs.KGS_KERNEL_SWEEP: "sweep", kgs.KGS_KERNEL_STREAM: "stream",
+             kgs.KGS_KERNEL_RESIDENT: "resident", kgs.KGS_KERNEL_TILE: "tile"}
+    updates = p.points * steps
+    paper_s = PAPER_A40_S[args.workload].get(n) if steps == 100 else None
+    out = {"metric": "lattice-point updates/s", "value": updates / wall,
+           "unit": "lattice-point updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+           "ms_per_step": wall * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": (updates / wall) / (updates / paper_s) if paper_s else None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{p.name} n={n}^{p.dim} box [{p.lo},{p.hi}) tau={p.tau} "
+                                  f"kappa1={p.kappa1} kappa2={p.kappa2} mu={p.mu} "
+                                  f"gamma={p.gamma}, {args.precision} state, {steps} DP-AVF2 steps",
+                      "points": p.points, "state": args.precision,
+                      "kernel": names.get(info.kernel, str(info.kernel)), "parallelism": "1 GPU"},
+           "run_s": wall,
+           "repeats_s": reps,
+           "host_inclusive_s": host_s,
+           "paper_a40_s": paper_s,
+           "speedup_vs_paper_a40": paper_s / wall if paper_s else None,
+           "host_inclusive_speedup_vs_paper_a40": paper_s / host_s if paper_s else None,
+           "energy_rel_drift": abs(e1 - e0) / abs(e0)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -420,6 +505,10 @@ def main():
         return bench_serving(args)
     if args.workload in ("1d", "2d"):
         return bench_small_dims(args)
+    if args.workload in ("paper2d", "paper3d"):
+        return bench_paper(args)
+    if args.n is None:
+        args.n = 256
     if args.steps is None:
         args.steps = 200
     import torch

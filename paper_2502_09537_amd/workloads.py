@@ -118,6 +118,47 @@ def accuracy_2d(level: int = 0, precision: int = FP64) -> Problem:
     return p
 
 
+def timing_2d(n: int = 1024, precision: int = FP64) -> Problem:
+    """The 2-D timing example of sec. 5.1 (Tab. time-2d): four Gaussian
+    solitons at (0,-3), (3,0), (0,3), (-3,0) on (-10,10)^2,
+    psi0 = (1+i) sum_j e^{-|x-x_j|^2}, u0 = sum_j tanh|x-x_j|^2,
+    v0 = e^{-|x|^2}; kappa1 = kappa2 = gamma = mu = 0.5, tau = 0.01 up to
+    t = 1 (100 steps)."""
+    p = Problem("timing2d", 2, n, -10.0, 10.0, 0.01, 100, kappa1=0.5, kappa2=0.5, mu=0.5,
+                gamma=0.5, precision=precision)
+    x, y = axes(2, n, p.lo, p.hi)
+    psi = np.zeros_like(x, dtype=np.complex128)
+    u = np.zeros_like(x)
+    for cx, cy in ((0.0, -3.0), (3.0, 0.0), (0.0, 3.0), (-3.0, 0.0)):
+        r2 = (x - cx) ** 2 + (y - cy) ** 2
+        psi += np.exp(-r2)
+        u += np.tanh(r2)
+    p.psi = (1.0 + 1.0j) * psi
+    p.u = u
+    p.v = np.exp(-(x ** 2 + y ** 2))
+    return p
+
+
+def timing_3d(n: int = 256, precision: int = FP64) -> Problem:
+    """The 3-D example of sec. 5.2 (Tab. gpu3d_list): two Gaussian packets
+    at x = -2 and x = 2 with the phase e^{0.01i(x+y+z)},
+    u0 = e^{-(x^2+y^2+(z-2)^2)} + sum_{s=+-1} e^{-((x+s sqrt3)^2+y^2+(z+1)^2)},
+    v0 = e^{-|x|^2} on (-10,10)^3; kappa1 = -0.4, kappa2 = 0.1,
+    gamma = 0.2, mu = 0.1, tau = 0.01 up to t = 1 (100 steps)."""
+    p = Problem("timing3d", 3, n, -10.0, 10.0, 0.01, 100, kappa1=-0.4, kappa2=0.1, mu=0.1,
+                gamma=0.2, precision=precision)
+    x, y, z = axes(3, n, p.lo, p.hi)
+    yz = y ** 2 + z ** 2
+    phase = np.exp(0.01j * (x + y + z))
+    p.psi = (np.exp(-((x + 2.0) ** 2) - yz) + np.exp(-((x - 2.0) ** 2) - yz)) * phase
+    r3 = np.sqrt(3.0)
+    p.u = (np.exp(-(x ** 2 + y ** 2 + (z - 2.0) ** 2))
+           + np.exp(-((x + r3) ** 2 + y ** 2 + (z + 1.0) ** 2))
+           + np.exp(-((x - r3) ** 2 + y ** 2 + (z + 1.0) ** 2)))
+    p.v = np.exp(-(x ** 2 + yz))
+    return p
+
+
 def random_problem(dim: int, n: int, seed: int, tau: float = 0.01, amp: float = 1.0,
                    precision: int = FP64, steps: int = 1, lo: float = -4.0, hi: float = 4.0,
                    params=None) -> Problem:

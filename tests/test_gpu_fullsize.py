@@ -111,3 +111,22 @@ def test_3d_256_sampled_points_match_the_oracle(prec):
         print("  block at", st, errs, flush=True)
         tol = 1e-12 if prec == workloads.FP64 else 1e-5
         assert max(errs.values()) <= tol, (st, errs)
+
+
+@pytest.mark.parametrize("which,n", [("2d", 2048), ("3d", 256)])
+def test_paper_timing_examples_full_size_conserve_energy(which, n):
+    """The paper's own GPU timing examples (Tab. time-2d at its largest grid,
+    Tab. gpu3d_list at 256^3 with kappa1 < 0) over their 100 steps: the
+    discrete energy is conserved in the launch configuration the library
+    picks for them."""
+    p = (workloads.timing_2d if which == "2d" else workloads.timing_3d)(n)
+    say("paper timing example", which, n, p.steps, "steps")
+    sim = kgs.simulation_from_problem(p)
+    try:
+        e0 = sim.energy()
+        sim.step(p.steps)
+        e1 = sim.energy()
+    finally:
+        sim.close()
+    print("  energy", e0, "->", e1, flush=True)
+    assert abs(e1 - e0) <= 1e-12 * abs(e0), (e0, e1)

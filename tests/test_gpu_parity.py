@@ -300,3 +300,13 @@ def test_parity_accuracy_example_2d_fp64(level):
 def test_parity_accuracy_example_2d_fp32(level):
     p = workloads.accuracy_2d(level, precision=workloads.FP32)
     assert_parity(p, p.steps, FP32_TOL)
+
+
+# ---------------------------------------------------------------------------
+# the paper's GPU timing examples (Tab. time-2d, Tab. gpu3d_list; kappa1 < 0
+# in 3-D) at reduced n: tiles, 3-D streaming and colour sweeps
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("which,n,steps", [("2d", 128, 20), ("3d", 96, 6), ("3d", 40, 10)])
+def test_parity_paper_timing_examples_fp64(which, n, steps):
+    p = (workloads.timing_2d if which == "2d" else workloads.timing_3d)(n)
+    assert_parity(p, steps, FP64_TOL)
