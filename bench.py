@@ -429,6 +429,7 @@ def bench_paper(args):
     repeated, and the same run with the state copied from and back to host
     memory around it (as the paper's GPU algorithm does), against the paper's
     A40 time for the same grid."""
+    import numpy as np
     import torch
 
     from paper_2502_09537_amd import kgs, workloads
@@ -460,15 +461,27 @@ def bench_paper(args):
         reps.append(a.elapsed_time(b) / 1e3)
     sim.close()
 
+    # The KGS_HOST boundary: the four float64 fields in host memory, as a
+    # caller holds them, copied in by kgs_init and out by kgs_read_state.
+    # The arrays are prepared outside the timed region.
+    cfg = kgs.config_of(p)
+    fields = [np.ascontiguousarray(a, dtype=np.float64) for a in (p.psi.real, p.psi.imag, p.u, p.v)]
+    outs = [np.ones_like(a) for a in fields]
+
     def host_run():
-        t = time.perf_counter()
-        s = kgs.simulation_from_problem(p, host=True)
-        s.step(steps)
-        s.read_state()
-        s.close()
-        return time.perf_counter() - t
+        t = [time.perf_counter()]
+        h = kgs.kgs_init(cfg, *[a.ctypes.data for a in fields], kgs.KGS_HOST, 0)
+        t.append(time.perf_counter())
+        kgs.kgs_step(h, steps)
+        kgs.kgs_sync(h)
+        t.append(time.perf_counter())
+        kgs.kgs_read_state(h, *[a.ctypes.data for a in outs], kgs.KGS_HOST)
+        t.append(time.perf_counter())
+        kgs.kgs_free(h)
+        t.append(time.perf_counter())
+        return t[-1] - t[0], {k: t[i + 1] - t[i] for i, k in enumerate(("init", "steps", "read", "free"))}
     host_run()
-    host_s = host_run()
+    host_s, host_parts = host_run()
 
     names = {kgs.KGS_KERNEL_SWEEP: "sweep", kgs.KGS_KERNEL_STREAM: "stream",
              kgs.KGS_KERNEL_RESIDENT: "resident", kgs.KGS_KERNEL_TILE: "tile"}
@@ -487,6 +500,8 @@ def bench_paper(args):
            "run_s": wall,
            "repeats_s": reps,
            "host_inclusive_s": host_s,
+           "host_inclusive_parts_s": host_parts,
+           "host_state_bytes_each_way": 4 * 8 * p.points,
            "paper_a40_s": paper_s,
            "speedup_vs_paper_a40": paper_s / wall if paper_s else None,
            "host_inclusive_speedup_vs_paper_a40": paper_s / host_s if paper_s else None,

@@ -239,11 +239,12 @@ int check_device(kgs_sim *s)
     return KGS_OK;
 }
 
-void free_device(void *p)
+// Frees device memory and returns the runtime's status; a NULL pointer is
+// a no-op.  Callers on an error path ignore the status (the first error is
+// the one reported); kgs_free reports it.
+hipError_t free_device(void *p)
 {
-    if (p && hipFree(p) != hipSuccess) {
-        // nothing useful to do: the handle is being torn down
-    }
+    return p ? hipFree(p) : hipSuccess;
 }
 
 // Device allocation of a handle: from its pool in stream order, or plain.
@@ -253,28 +254,27 @@ hipError_t alloc_device(kgs_sim *s, void **p, size_t bytes)
     return hipMalloc(p, bytes);
 }
 
-void free_handle_memory(kgs_sim *s, void *p)
+hipError_t free_handle_memory(kgs_sim *s, void *p)
 {
-    if (!p) return;
-    if (s->pool) {
-        if (hipFreeAsync(p, s->stream) != hipSuccess) {
-        }
-    } else {
-        free_device(p);
-    }
+    if (!p) return hipSuccess;
+    return s->pool ? hipFreeAsync(p, s->stream) : free_device(p);
 }
 
-void release(kgs_sim *s)
+// Releases everything a handle holds on the device and in pinned host
+// memory, and returns the first error of the runtime (every release is
+// attempted regardless).
+hipError_t release(kgs_sim *s)
 {
-    if (!s) return;
-    free_handle_memory(s, s->state);
-    free_handle_memory(s, s->state2);
-    free_handle_memory(s, s->partials);
-    if (s->host_out && hipHostFree(s->host_out) != hipSuccess) {
-    }
+    if (!s) return hipSuccess;
+    kgs::FirstError err;
+    err(free_handle_memory(s, s->state));
+    err(free_handle_memory(s, s->state2));
+    err(free_handle_memory(s, s->partials));
+    if (s->host_out) err(hipHostFree(s->host_out));
     s->state = s->state2 = nullptr;
     s->partials = nullptr;
     s->host_out = nullptr;
+    return err.e;
 }
 
 // Copy four float64 boundary arrays into the colour-split state.
@@ -661,8 +661,9 @@ int kgs_free(kgs_sim *s)
         hipError_t e = hipStreamSynchronize(s->stream);
         if (e != hipSuccess) rc = hip_fail(s, e, "hipStreamSynchronize");
     }
+    const hipError_t e = release(s);
+    if (rc == KGS_OK && e != hipSuccess) rc = hip_fail(s, e, "releasing device memory");
     if (rc != KGS_OK) g_err = s->err;
-    release(s);
     delete s;
     return rc;
 }

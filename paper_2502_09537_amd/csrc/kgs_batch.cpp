@@ -81,40 +81,28 @@ int bhip(kgs_batch *b, hipError_t e, const char *what)
 
 thread_local std::string g_batch_err;
 
-void destroy(kgs_batch *b)
+// Releases everything the batch holds; the first runtime error, if any.
+hipError_t destroy(kgs_batch *b)
 {
-    for (auto &kv : b->graphs)
-        if (hipGraphExecDestroy(kv.second) != hipSuccess) {
-        }
+    kgs::FirstError err;
+    for (auto &kv : b->graphs) err(hipGraphExecDestroy(kv.second));
     b->graphs.clear();
     for (auto &c : b->classes) {
-        if (c.d_members && hipFree(c.d_members) != hipSuccess) {
-        }
-        if (c.h_members && hipHostFree(c.h_members) != hipSuccess) {
-        }
-        if (c.d_res && hipFree(c.d_res) != hipSuccess) {
-        }
-        if (c.h_res && hipHostFree(c.h_res) != hipSuccess) {
-        }
-        if (c.d_s2 && hipFree(c.d_s2) != hipSuccess) {
-        }
-        if (c.h_s2 && hipHostFree(c.h_s2) != hipSuccess) {
-        }
+        if (c.d_members) err(hipFree(c.d_members));
+        if (c.h_members) err(hipHostFree(c.h_members));
+        if (c.d_res) err(hipFree(c.d_res));
+        if (c.h_res) err(hipHostFree(c.h_res));
+        if (c.d_s2) err(hipFree(c.d_s2));
+        if (c.h_s2) err(hipHostFree(c.h_s2));
     }
-    if (b->d_steps && hipFree(b->d_steps) != hipSuccess) {
-    }
-    if (b->h_steps && hipHostFree(b->h_steps) != hipSuccess) {
-    }
-    if (b->d_kinds && hipFree(b->d_kinds) != hipSuccess) {
-    }
-    if (b->h_kinds && hipHostFree(b->h_kinds) != hipSuccess) {
-    }
-    if (b->ev_in && hipEventDestroy(b->ev_in) != hipSuccess) {
-    }
-    if (b->ev_out && hipEventDestroy(b->ev_out) != hipSuccess) {
-    }
-    if (b->own && hipStreamDestroy(b->own) != hipSuccess) {
-    }
+    if (b->d_steps) err(hipFree(b->d_steps));
+    if (b->h_steps) err(hipHostFree(b->h_steps));
+    if (b->d_kinds) err(hipFree(b->d_kinds));
+    if (b->h_kinds) err(hipHostFree(b->h_kinds));
+    if (b->ev_in) err(hipEventDestroy(b->ev_in));
+    if (b->ev_out) err(hipEventDestroy(b->ev_out));
+    if (b->own) err(hipStreamDestroy(b->own));
+    return err.e;
 }
 
 // Copy every member's current state buffer (the 3-D streaming kernel swaps
@@ -483,15 +471,18 @@ int kgs_batch_step(kgs_batch *b, int64_t nsteps)
             hipError_t le = enqueue_uniform(b, nsteps);
             e = hipStreamEndCapture(b->own, &g);
             if (le != hipSuccess) {
-                if (g && hipGraphDestroy(g) != hipSuccess) {
-                }
+                // the launch error is the one reported; the graph is discarded
+                if (g) (void)hipGraphDestroy(g);
                 return bhip(b, le, "batched sweep launch (capture)");
             }
             if (e != hipSuccess) return bhip(b, e, "hipStreamEndCapture");
             e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-            if (hipGraphDestroy(g) != hipSuccess) {
-            }
+            const hipError_t gd = hipGraphDestroy(g);
             if (e != hipSuccess) return bhip(b, e, "hipGraphInstantiate");
+            if (gd != hipSuccess) {
+                (void)hipGraphExecDestroy(ge);  // the first error is the one reported
+                return bhip(b, gd, "hipGraphDestroy");
+            }
             it = b->graphs.emplace(nsteps, ge).first;
         }
         if ((e = hipGraphLaunch(it->second, b->own)) != hipSuccess) return bhip(b, e, "hipGraphLaunch");
@@ -528,10 +519,10 @@ int kgs_batch_step_each(kgs_batch *b, const int64_t *nsteps)
     if (need > b->kinds_cap) {
         // the previous table may still be read by queued work
         if ((e = hipStreamSynchronize(b->own)) != hipSuccess) return bhip(b, e, "hipStreamSynchronize");
-        if (b->d_kinds && hipFree(b->d_kinds) != hipSuccess) {
-        }
-        if (b->h_kinds && hipHostFree(b->h_kinds) != hipSuccess) {
-        }
+        kgs::FirstError err;
+        if (b->d_kinds) err(hipFree(b->d_kinds));
+        if (b->h_kinds) err(hipHostFree(b->h_kinds));
+        if (!err.ok()) return bhip(b, err.e, "releasing the schedule");
         b->d_kinds = nullptr;
         b->h_kinds = nullptr;
         b->kinds_cap = 0;
@@ -614,7 +605,7 @@ int kgs_batch_free(kgs_batch *b)
     int rc = KGS_OK;
     if (hipSetDevice(b->device) != hipSuccess || hipStreamSynchronize(b->own) != hipSuccess)
         rc = KGS_EDEVICE;
-    destroy(b);
+    if (destroy(b) != hipSuccess) rc = KGS_EDEVICE;
     delete b;
     return rc;
 }

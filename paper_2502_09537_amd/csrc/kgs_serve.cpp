@@ -144,6 +144,9 @@ struct kgs_server {
     std::vector<hipEvent_t> spare_events;
     int64_t rounds = 0;
     std::string err;
+    // the first failed release of a resource (reported by kgs_server_free);
+    // the copy worker updates it under `mu`
+    kgs::FirstError release_err;
     // result-copy worker
     std::thread copier;
     hipStream_t copy_out = nullptr;
@@ -210,8 +213,7 @@ int take_slot(kgs_server *s)
         if (hipMalloc(reinterpret_cast<void **>(&c.d), bytes) != hipSuccess) return -1;
         if (hipHostMalloc(reinterpret_cast<void **>(&c.h), bytes, hipHostMallocDefault) !=
             hipSuccess) {
-            if (hipFree(c.d) != hipSuccess) {
-            }
+            s->release_err(hipFree(c.d));
             return -1;
         }
         const int base = static_cast<int>(s->energy.size()) * kSlotChunk;
@@ -261,10 +263,8 @@ Ring::Slot *ring_take(kgs_server *s, int lane, size_t bytes, int &rc)
         return nullptr;
     }
     if (sl.cap < bytes) {
-        if (sl.h && hipHostFree(sl.h) != hipSuccess) {
-        }
-        if (sl.d && hipFree(sl.d) != hipSuccess) {
-        }
+        if (sl.h) s->release_err(hipHostFree(sl.h));
+        if (sl.d) s->release_err(hipFree(sl.d));
         sl.h = sl.d = nullptr;
         sl.cap = 0;
         size_t cap = 4096;
@@ -302,13 +302,11 @@ void free_request_memory(kgs_server *s, Request *r)
         r->sim = nullptr;
     }
     if (r->dev_in) {
-        if (hipFreeAsync(r->dev_in, s->user) != hipSuccess) {
-        }
+        s->release_err(hipFreeAsync(r->dev_in, s->user));
         r->dev_in = nullptr;
     }
     if (r->staging) {
-        if (hipFreeAsync(r->staging, s->copy) != hipSuccess) {
-        }
+        s->release_err(hipFreeAsync(r->staging, s->copy));
         r->staging = nullptr;
     }
 }
@@ -363,8 +361,7 @@ void admit(kgs_server *s)
         else
             msg = std::string("input copy: ") + hipGetErrorName(e);
         if (r->dev_in) {
-            if (hipFreeAsync(r->dev_in, st) != hipSuccess) {
-            }
+            s->release_err(hipFreeAsync(r->dev_in, st));
             r->dev_in = nullptr;
         }
         if (rc == KGS_OK && (r->slot = take_slot(s)) < 0) {
@@ -425,8 +422,9 @@ void start_retire(kgs_server *s, Request *r)
 // on its own stream, returns the device buffers to the pool.
 void copy_worker(kgs_server *s)
 {
-    if (hipSetDevice(s->device) != hipSuccess) {
-    }
+    // without the server's device current no copy may run: every job then
+    // fails with this error
+    const hipError_t dev = hipSetDevice(s->device);
     for (;;) {
         CopyJob job;
         {
@@ -436,18 +434,19 @@ void copy_worker(kgs_server *s)
             job = s->jobs.front();
             s->jobs.pop_front();
         }
-        double *h = new (std::nothrow) double[job.n];
-        hipError_t e = h ? hipMemcpyAsync(h, job.src, job.n * sizeof(double), hipMemcpyDeviceToHost,
-                                          s->copy_out)
-                         : hipErrorOutOfMemory;
+        double *h = dev == hipSuccess ? new (std::nothrow) double[job.n] : nullptr;
+        hipError_t e = dev != hipSuccess ? dev
+                       : h ? hipMemcpyAsync(h, job.src, job.n * sizeof(double),
+                                            hipMemcpyDeviceToHost, s->copy_out)
+                           : hipErrorOutOfMemory;
         if (e == hipSuccess) e = hipStreamSynchronize(s->copy_out);
-        if (hipFreeAsync(job.src, s->copy_out) != hipSuccess) {
-        }
+        const hipError_t freed = dev == hipSuccess ? hipFreeAsync(job.src, s->copy_out) : dev;
         if (e != hipSuccess) {
             delete[] h;
             h = nullptr;
         }
         std::lock_guard<std::mutex> lk(s->mu);
+        s->release_err(freed);
         s->done.push_back({job.id, h, e, now_s() - s->t0});
         --s->in_flight;
         s->cv_done.notify_all();
@@ -1153,29 +1152,22 @@ int kgs_server_free(kgs_server *s)
     if (hipStreamSynchronize(s->user) != hipSuccess) rc = KGS_EDEVICE;
     for (hipEvent_t e : s->ahead) give_event(s, e);
     for (hipEvent_t e : s->spare_events)
-        if (hipEventDestroy(e) != hipSuccess) {
-        }
+        s->release_err(hipEventDestroy(e));
     for (auto &g : s->ring)
         for (auto &sl : g.slots) {
-            if (sl.h && hipHostFree(sl.h) != hipSuccess) {
-            }
-            if (sl.d && hipFree(sl.d) != hipSuccess) {
-            }
-            if (sl.ev && hipEventDestroy(sl.ev) != hipSuccess) {
-            }
+            if (sl.h) s->release_err(hipHostFree(sl.h));
+            if (sl.d) s->release_err(hipFree(sl.d));
+            if (sl.ev) s->release_err(hipEventDestroy(sl.ev));
         }
     for (auto &c : s->energy) {
-        if (c.d && hipFree(c.d) != hipSuccess) {
-        }
-        if (c.h && hipHostFree(c.h) != hipSuccess) {
-        }
+        if (c.d) s->release_err(hipFree(c.d));
+        if (c.h) s->release_err(hipHostFree(c.h));
     }
-    if (s->ev_submit && hipEventDestroy(s->ev_submit) != hipSuccess) {
-    }
+    if (s->ev_submit) s->release_err(hipEventDestroy(s->ev_submit));
     for (hipStream_t st : {s->lane[0], s->lane[1], s->copy, s->copy_out})
-        if (st && hipStreamDestroy(st) != hipSuccess) {
-        }
+        if (st) s->release_err(hipStreamDestroy(st));
     if (s->pool && hipMemPoolDestroy(s->pool) != hipSuccess) rc = KGS_EDEVICE;
+    if (!s->release_err.ok()) rc = KGS_EDEVICE;
     delete s;
     return rc;
 }

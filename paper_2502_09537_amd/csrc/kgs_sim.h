@@ -32,6 +32,18 @@ struct kgs_sim {
 
 namespace kgs {
 
+// The first failure of a series of runtime calls that are all attempted,
+// such as the releases of every resource of an object, which continue after
+// one of them has failed.
+struct FirstError {
+    hipError_t e = hipSuccess;
+    void operator()(hipError_t x)
+    {
+        if (e == hipSuccess) e = x;
+    }
+    bool ok() const { return e == hipSuccess; }
+};
+
 // Handles for the server: device memory from `pool` in the order of `stream`
 // (no host synchronisation anywhere), initial state from float64 device
 // arrays read by a scatter kernel on the stream, the library's default

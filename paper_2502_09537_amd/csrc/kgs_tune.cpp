@@ -147,12 +147,11 @@ extern "C" int kgs_autotune(kgs_sim *s, int32_t steps, int32_t use_cache, kgs_tu
         }
     }
     if (hipStreamSynchronize(s->stream) != hipSuccess && rc == KGS_OK) rc = KGS_EDEVICE;
-    if (a && hipEventDestroy(a) != hipSuccess) {
-    }
-    if (b && hipEventDestroy(b) != hipSuccess) {
-    }
-    if (hipFree(backup) != hipSuccess) {
-    }
+    kgs::FirstError rel;
+    if (a) rel(hipEventDestroy(a));
+    if (b) rel(hipEventDestroy(b));
+    rel(hipFree(backup));
+    if (!rel.ok() && rc == KGS_OK) rc = KGS_EDEVICE;
     if (rc != KGS_OK) {
         s->err = "autotune: a HIP call failed";
         kgs_set_tuning(s, &original);
