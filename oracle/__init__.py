@@ -155,6 +155,41 @@ def checkerboard_order(dim: int, n: int) -> np.ndarray:
     return order
 
 
+def block_splitting_rows(n: int, n_proc: int):
+    """Row partition of Algorithm 2 (sec. 4.2) on an n x n grid, 0-based
+    rows along axis 0: row 0 is the first boundary row (j_0), and the other
+    n - 1 rows are n_proc blocks, each followed by one separator row
+    (j_1, ..., j_{n_proc}; the last separator is row n - 1, the periodic
+    neighbour of row 0).  The n - 1 - n_proc block rows are shared as evenly
+    as possible.  Returns (blocks, separators): a list of row ranges and the
+    list of separator rows."""
+    if n_proc < 1 or n - 1 - n_proc < n_proc:
+        raise ValueError("every block needs at least one row")
+    inner = n - 1 - n_proc
+    blocks, seps, row = [], [], 1
+    for l in range(n_proc):
+        size = inner // n_proc + (1 if l < inner % n_proc else 0)
+        blocks.append(range(row, row + size))
+        seps.append(row + size)
+        row += size + 1
+    assert row == n and seps[-1] == n - 1
+    return blocks, seps
+
+
+def block_splitting_order(n: int, n_proc: int, block_sequence=None) -> np.ndarray:
+    """The serial update order that the block-splitting strategy of
+    Algorithm 2 executes on a 2-D n x n grid (linear index row * n + col):
+    the boundary row j_0, then every block row by row (the blocks are
+    independent, so `block_sequence` may list them in any order, which is
+    what running them in parallel amounts to), then the separator rows in
+    ascending order; columns ascending within a row.  The adjoint half step
+    visits the same points in reverse, as Algorithm 2 does."""
+    blocks, seps = block_splitting_rows(n, n_proc)
+    seq = range(n_proc) if block_sequence is None else block_sequence
+    rows = [0] + [r for l in seq for r in blocks[l]] + seps
+    return np.array([r * n + c for r in rows for c in range(n)], dtype=np.int64)
+
+
 def step(grid: Grid, tau: float, s: State, nsteps: int = 1) -> State:
     """nsteps DP-AVF2 steps in the checkerboard order, in place."""
     _check(grid, *s.arrays())

@@ -157,6 +157,54 @@ def test_random_update_orders_conserve_energy():
         assert abs(oracle.energy(grid, s) - e0) <= 1e-13 * abs(e0)
 
 
+def test_block_splitting_orders_conserve_energy_and_blocks_are_independent():
+    # Algorithm 2 (the CPU strategy of sec. 4.2): each process count gives
+    # its own update order and so its own DP-AVF2 scheme; each conserves the
+    # energy (the block-splitting energy experiments of sec. 5), each is
+    # reversed by the step with -tau, and the blocks can run in any order
+    # (in parallel) without changing a bit of the result.
+    n = 16
+    grid = Grid(2, n, -4.0, 4.0, 1.0, 1.0, 1.0, 1.0)
+    p = workloads.gaussian_problem(2, n, 11, -4.0, 4.0, 0.05, 1, params=(1, 1, 1, 1))
+    finals = []
+    for n_proc in (1, 2, 3, 4, 7):
+        order = oracle.block_splitting_order(n, n_proc)
+        assert sorted(order.tolist()) == list(range(n * n))
+        s = State.from_fields(p.psi, p.u, p.v)
+        e0 = oracle.energy(grid, s)
+        oracle.step_order(grid, 0.05, s, order, 40)
+        assert abs(oracle.energy(grid, s) - e0) <= 1e-13 * abs(e0)
+        finals.append(s.copy())
+        if n_proc > 1:
+            rev = oracle.block_splitting_order(n, n_proc, block_sequence=range(n_proc - 1, -1, -1))
+            assert not np.array_equal(rev, order)
+            t = State.from_fields(p.psi, p.u, p.v)
+            oracle.step_order(grid, 0.05, t, rev, 40)
+            for a, b in zip(s.arrays(), t.arrays()):
+                assert np.array_equal(a, b)
+        back = s.copy()
+        oracle.step_order(grid, -0.05, back, order, 40)
+        for a, b in zip(back.arrays(), (p.psi.real, p.psi.imag, p.u, p.v)):
+            assert np.max(np.abs(a - b)) <= 1e-12
+    # different process counts are different schemes
+    assert not np.array_equal(finals[1].P, finals[3].P)
+
+
+def test_block_splitting_rows_follow_algorithm_2():
+    blocks, seps = oracle.block_splitting_rows(16, 3)
+    # row 0, blocks of 4, 4 and 4 rows, each followed by a separator row
+    assert [list(b) for b in blocks] == [[1, 2, 3, 4], [6, 7, 8, 9], [11, 12, 13, 14]]
+    assert seps == [5, 10, 15]
+    # a block reads only its own rows, row 0 and the separators: no two
+    # blocks are neighbours (periodic in the rows)
+    owner = {r: l for l, b in enumerate(blocks) for r in b}
+    for r, l in owner.items():
+        for nb in ((r - 1) % 16, (r + 1) % 16):
+            assert owner.get(nb, l) == l
+    with pytest.raises(ValueError):
+        oracle.block_splitting_rows(8, 4)
+
+
 # ---------------------------------------------------------------------------
 # Update order structure
 # ---------------------------------------------------------------------------
