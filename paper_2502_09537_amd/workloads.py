@@ -220,6 +220,19 @@ def gaussian_fields_torch(p: Problem, device="cuda"):
         torch.zeros_like(u)
 
 
+def random_fields_torch(dim: int, n: int, seed: int, amp: float = 0.5, device="cuda"):
+    """I.i.d. uniform fields in [-amp, amp] of shape (n,)*dim, float64,
+    generated on a torch device from a seeded generator (for grids too large
+    to build in host memory): (psi_re, psi_im, u, v)."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    shape = (n,) * dim
+    return tuple((2.0 * torch.rand(shape, generator=g, dtype=torch.float64, device=device) - 1.0)
+                 * amp for _ in range(4))
+
+
 def batched_instances(count: int = 64, seed: int = 20250213, steps: int = 500,
                       precision: int = FP64, sizes=None) -> List[Problem]:
     """Batched workload: `count` 2-D instances on [-16,16)^2, tau = 0.005,

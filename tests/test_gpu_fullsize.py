@@ -113,6 +113,63 @@ def test_3d_256_sampled_points_match_the_oracle(prec):
         assert max(errs.values()) <= tol, (st, errs)
 
 
+@pytest.mark.parametrize("prec", [workloads.FP64, workloads.FP32])
+def test_3d_1024_sampled_points_match_the_oracle(prec):
+    """A 1024^3 grid, whose field planes hold 2^29 points (8.6 GB in
+    float64): every offset into the state is beyond 32 bits.  Random fields
+    made on the device go in through the device boundary; after 4 steps
+    (streaming launches and the closing sweep) six 24^3 sub-blocks, two of
+    them across the periodic edges, match the oracle in their central 4^3
+    points, and the float64 energy is conserved."""
+    import torch
+
+    import oracle
+
+    n, steps, B, lo_i, hi_i = 1024, 4, 24, 10, 14
+    lo, hi, tau = -8.0, 8.0, 0.002
+    say("3-D 1024^3 x 4 steps, sampled oracle", prec)
+    cfg = kgs.make_config(3, n, lo, hi, tau, 1.0, 1.0, 1.0, 1.0, prec)
+    fields = workloads.random_fields_torch(3, n, seed=23)
+    rng = np.random.default_rng(11)
+    starts = [(0, 0, 0), (1012, 500, 1010)] + [
+        tuple(int(x) for x in 2 * rng.integers(0, n // 2, size=3)) for _ in range(4)]
+    index = [[torch.from_numpy((np.arange(B) + s) % n).to("cuda") for s in st] for st in starts]
+
+    def block(t, ix):
+        return t.index_select(0, ix[0]).index_select(1, ix[1]).index_select(2, ix[2]).cpu().numpy()
+
+    initial = [[block(f, ix) for f in fields] for ix in index]
+    stream = torch.cuda.current_stream()
+    h = kgs.kgs_init(cfg, *[f.data_ptr() for f in fields], kgs.KGS_DEVICE, stream.cuda_stream)
+    try:
+        del fields
+        torch.cuda.synchronize()
+        assert kgs.kgs_get_info(h).kernel == kgs.KGS_KERNEL_STREAM
+        e0 = kgs.kgs_energy(h)
+        kgs.kgs_step(h, steps)
+        e1 = kgs.kgs_energy(h)
+        out = [torch.empty((n,) * 3, dtype=torch.float64, device="cuda") for _ in range(4)]
+        kgs.kgs_read_state(h, *[o.data_ptr() for o in out], kgs.KGS_DEVICE)
+    finally:
+        kgs.kgs_free(h)
+    print("  energy", e0, "->", e1, flush=True)
+    if prec == workloads.FP64:
+        assert abs(e1 - e0) <= 1e-12 * abs(e0), (e0, e1)
+    hgrid = (hi - lo) / n
+    g = oracle.Grid(3, B, 0.0, B * hgrid, 1.0, 1.0, 1.0, 1.0)
+    c = (slice(lo_i, hi_i),) * 3
+    tol = 1e-12 if prec == workloads.FP64 else 1e-5
+    for st, ix, (P0, Q0, U0, V0) in zip(starts, index, initial):
+        s0 = oracle.State(P0, Q0, U0, V0)
+        oracle.step(g, tau, s0, steps)
+        got = [block(o, ix)[c] for o in out]
+        ref = [a[c] for a in s0.arrays()]
+        scale = max(float(np.max(np.abs(a))) for a in ref)
+        err = max(float(np.max(np.abs(x - y))) for x, y in zip(got, ref)) / scale
+        print("  block at", st, err, flush=True)
+        assert err <= tol, (st, err)
+
+
 @pytest.mark.parametrize("which,n", [("2d", 2048), ("3d", 256)])
 def test_paper_timing_examples_full_size_conserve_energy(which, n):
     """The paper's own GPU timing examples (Tab. time-2d at its largest grid,
