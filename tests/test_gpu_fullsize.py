@@ -114,29 +114,32 @@ def test_3d_256_sampled_points_match_the_oracle(prec):
 
 
 @pytest.mark.parametrize("prec", [workloads.FP64, workloads.FP32])
-def test_3d_1024_sampled_points_match_the_oracle(prec):
-    """A 1024^3 grid, whose field planes hold 2^29 points (8.6 GB in
-    float64): every offset into the state is beyond 32 bits.  Random fields
-    made on the device go in through the device boundary; after 4 steps
-    (streaming launches and the closing sweep) six 24^3 sub-blocks, two of
-    them across the periodic edges, match the oracle in their central 4^3
-    points, and the float64 energy is conserved."""
+@pytest.mark.parametrize("dim,n", [(3, 1024), (2, 32768)])
+def test_largest_grids_sampled_points_match_the_oracle(dim, n, prec):
+    """Grids of 2^30 points (3-D 1024^3 and 2-D 32768^2): a colour's pair
+    plane is 8.6 GB in float64, so every state offset is beyond 32 bits.
+    Random fields made on the device go in through the device boundary;
+    after 4 steps (streaming launches and the closing sweep) six 24^dim
+    sub-blocks, two of them across the periodic edges, match the oracle in
+    their central 4^dim points, and the float64 energy is conserved."""
     import torch
 
     import oracle
 
-    n, steps, B, lo_i, hi_i = 1024, 4, 24, 10, 14
+    steps, B, lo_i, hi_i = 4, 24, 10, 14
     lo, hi, tau = -8.0, 8.0, 0.002
-    say("3-D 1024^3 x 4 steps, sampled oracle", prec)
-    cfg = kgs.make_config(3, n, lo, hi, tau, 1.0, 1.0, 1.0, 1.0, prec)
-    fields = workloads.random_fields_torch(3, n, seed=23)
+    say(f"{dim}-D {n}^{dim} x {steps} steps, sampled oracle", prec)
+    cfg = kgs.make_config(dim, n, lo, hi, tau, 1.0, 1.0, 1.0, 1.0, prec)
+    fields = workloads.random_fields_torch(dim, n, seed=23)
     rng = np.random.default_rng(11)
-    starts = [(0, 0, 0), (1012, 500, 1010)] + [
-        tuple(int(x) for x in 2 * rng.integers(0, n // 2, size=3)) for _ in range(4)]
+    starts = [(0,) * dim, tuple(n - 12 if a % 2 == 0 else n // 2 - 12 for a in range(dim))] + [
+        tuple(int(x) for x in 2 * rng.integers(0, n // 2, size=dim)) for _ in range(4)]
     index = [[torch.from_numpy((np.arange(B) + s) % n).to("cuda") for s in st] for st in starts]
 
     def block(t, ix):
-        return t.index_select(0, ix[0]).index_select(1, ix[1]).index_select(2, ix[2]).cpu().numpy()
+        for a, sel in enumerate(ix):
+            t = t.index_select(a, sel)
+        return t.cpu().numpy()
 
     initial = [[block(f, ix) for f in fields] for ix in index]
     stream = torch.cuda.current_stream()
@@ -148,7 +151,7 @@ def test_3d_1024_sampled_points_match_the_oracle(prec):
         e0 = kgs.kgs_energy(h)
         kgs.kgs_step(h, steps)
         e1 = kgs.kgs_energy(h)
-        out = [torch.empty((n,) * 3, dtype=torch.float64, device="cuda") for _ in range(4)]
+        out = [torch.empty((n,) * dim, dtype=torch.float64, device="cuda") for _ in range(4)]
         kgs.kgs_read_state(h, *[o.data_ptr() for o in out], kgs.KGS_DEVICE)
     finally:
         kgs.kgs_free(h)
@@ -156,8 +159,8 @@ def test_3d_1024_sampled_points_match_the_oracle(prec):
     if prec == workloads.FP64:
         assert abs(e1 - e0) <= 1e-12 * abs(e0), (e0, e1)
     hgrid = (hi - lo) / n
-    g = oracle.Grid(3, B, 0.0, B * hgrid, 1.0, 1.0, 1.0, 1.0)
-    c = (slice(lo_i, hi_i),) * 3
+    g = oracle.Grid(dim, B, 0.0, B * hgrid, 1.0, 1.0, 1.0, 1.0)
+    c = (slice(lo_i, hi_i),) * dim
     tol = 1e-12 if prec == workloads.FP64 else 1e-5
     for st, ix, (P0, Q0, U0, V0) in zip(starts, index, initial):
         s0 = oracle.State(P0, Q0, U0, V0)
