@@ -118,7 +118,10 @@ int kgs_write_state(kgs_sim *sim, const double *psi_re, const double *psi_im, co
 /* Wait until all work enqueued for the handle has finished. */
 int kgs_sync(kgs_sim *sim);
 
-/* Release the device state.  NULL is accepted.  Waits for the stream. */
+/* Release the device state.  NULL is accepted.  Waits for the stream.  The
+ * handle is gone afterwards whatever the status: every release is
+ * attempted, and KGS_EDEVICE (message from kgs_last_error(NULL)) reports a
+ * failed wait or release. */
 int kgs_free(kgs_sim *sim);
 
 /* Message of the last failure on this handle (or, for NULL, of the last
@@ -233,7 +236,9 @@ int kgs_batch_step_each(kgs_batch *b, const int64_t *nsteps);
  * run in a hipGraph the first time K is used and replays it afterwards. */
 int kgs_batch_set_graph(kgs_batch *b, int32_t enable);
 
-/* Wait for the batch's work and release it (not the member simulations). */
+/* Wait for the batch's work and release it (not the member simulations).
+ * The batch is gone afterwards whatever the status; KGS_EDEVICE reports a
+ * failed wait or release (every release is attempted). */
 int kgs_batch_free(kgs_batch *b);
 
 /* Message of the last failure of b (or of kgs_batch_create for NULL). */
@@ -327,7 +332,10 @@ int kgs_server_cancel(kgs_server *s, int64_t id);
 
 int kgs_server_stats(const kgs_server *s, kgs_server_stats_t *st);
 
-/* Wait for the server's work and release everything it holds. */
+/* Wait for the server's work and release everything it holds.  The server
+ * is gone afterwards whatever the status; KGS_EDEVICE reports a failed wait
+ * or a failed release, including one of a request's buffers earlier in the
+ * server's life (every release is attempted). */
 int kgs_server_free(kgs_server *s);
 
 const char *kgs_server_last_error(const kgs_server *s);
