@@ -122,3 +122,16 @@ def test_required_bytes(L):
     cfg2s = good(dim=2, n=64)  # resident: one state
     small2 = 8 * (64 ** 2 // 2) * 8
     assert small2 <= kgs.required_bytes(cfg2s) < small2 + (1 << 20)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    # there is no fallback path: without the built library every entry of
+    # the binding raises
+    monkeypatch.setattr(kgs, "LIB_PATH", str(tmp_path / "libkgs.so"))
+    monkeypatch.setattr(kgs, "_lib", None)
+    with pytest.raises(ImportError):
+        kgs.lib()
+    with pytest.raises(ImportError):
+        kgs.last_error(None)
+    with pytest.raises(ImportError):
+        kgs.kgs_step(None, 1)
