@@ -641,6 +641,9 @@ def main():
         # actual HBM traffic rate of the dominant kernel, against the peak and
         # against what a plain device copy reaches on this GPU
         out["roofline"]["traffic_GBs"] = traffic / avg_launch_s / 1e9
+        # measured HBM bytes per lattice-point update (algorithmic: 64 / 32)
+        out["roofline"]["traffic_bytes_per_update"] = traffic / (
+            p.points * (spl if per == 1 else 0.5))
         copy_gbs = device_copy_gbs(torch, stream, 1024)
         out["roofline"]["copy_GBs"] = copy_gbs
         out["roofline"]["traffic_frac_of_peak"] = traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS
