@@ -56,7 +56,8 @@ enum {
                            axis would share a colour and be neighbours, so the
                            colour classes would not be independent (sec. 4.2) */
     KGS_ESINGULAR = 3,  /* the constant 2x2 (u, v) matrix is singular or its
-                           inverse is not finite (Algorithm 1, step 3)        */
+                           inverse, which Algorithm 1 precomputes, is not
+                           finite                                             */
     KGS_ENOMEM = 4,     /* device allocation failed or exceeds the limit      */
     KGS_EDEVICE = 5,    /* a HIP call failed; see kgs_last_error              */
     KGS_ENONFINITE = 6, /* the energy is NaN or infinite                      */
@@ -109,9 +110,11 @@ int kgs_energy(kgs_sim *sim, double *energy);
 int kgs_read_state(kgs_sim *sim, double *psi_re, double *psi_im, double *u, double *v_t,
                    int32_t mem);
 
-/* Replace the current state (float64 arrays as above); enqueued on the
- * stream.  Reading the state, writing it back and stepping gives bitwise the
- * same result as stepping without the round trip (float64 state). */
+/* Replace the current state (float64 arrays as above).  The copy runs on
+ * the handle's stream after the work already enqueued, and the call returns
+ * when it has finished.  Reading the state, writing it back and stepping
+ * gives bitwise the same result as stepping without the round trip (float64
+ * state). */
 int kgs_write_state(kgs_sim *sim, const double *psi_re, const double *psi_im, const double *u,
                     const double *v_t, int32_t mem);
 

@@ -131,8 +131,9 @@ void kgso_psi_update(const kgso_grid *g, double tau, double *P, double *Q, const
     Q[idx] = cimag(psi_new);
 }
 
-/* Inverse of the constant 2x2 matrix of the (U, V) equations (Algorithm 1,
- * step 3):  [[1, -tau/2], [beta, 1]]^{-1} = (1/det) [[1, tau/2], [-beta, 1]],
+/* Inverse of the constant 2x2 matrix of the (U, V) equations, which
+ * Algorithm 1 computes once before the time loop:
+ *   [[1, -tau/2], [beta, 1]]^{-1} = (1/det) [[1, tau/2], [-beta, 1]],
  * beta = d tau k2/h^2 + tau mu^2/2, det = 1 + beta tau/2.
  *
  * 1/det is kept as an unevaluated sum of two doubles (computed in binary128).
