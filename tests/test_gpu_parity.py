@@ -310,3 +310,9 @@ def test_parity_accuracy_example_2d_fp32(level):
 def test_parity_paper_timing_examples_fp64(which, n, steps):
     p = (workloads.timing_2d if which == "2d" else workloads.timing_3d)(n)
     assert_parity(p, steps, FP64_TOL)
+
+
+@pytest.mark.parametrize("which,n,steps", [("2d", 128, 20), ("3d", 96, 6)])
+def test_parity_paper_timing_examples_fp32(which, n, steps):
+    p = (workloads.timing_2d if which == "2d" else workloads.timing_3d)(n, workloads.FP32)
+    assert_parity(p, steps, FP32_TOL)
