@@ -119,8 +119,9 @@ def test_largest_grids_sampled_points_match_the_oracle(dim, n, prec):
     """Grids of 2^30 points (3-D 1024^3, 2-D 32768^2, 1-D 2^30): a colour's
     pair plane is 8.6 GB in float64, so every state offset is beyond 32
     bits.  Random fields made on the device go in through the device
-    boundary; after 4 steps (streaming launches and the closing sweep in
-    2-D and 3-D, colour sweeps in 1-D) six 24^dim sub-blocks, two of them
+    boundary; after 4 steps (the library's default launches: tiles for
+    2-D float64, streaming otherwise in 2-D and 3-D, colour sweeps in 1-D)
+    six 24^dim sub-blocks, two of them
     across the periodic edges, match the oracle in their central 4^dim
     points, and the float64 energy is conserved."""
     import torch
@@ -148,7 +149,9 @@ def test_largest_grids_sampled_points_match_the_oracle(dim, n, prec):
     try:
         del fields
         torch.cuda.synchronize()
-        expected = kgs.KGS_KERNEL_SWEEP if dim == 1 else kgs.KGS_KERNEL_STREAM
+        expected = (kgs.KGS_KERNEL_SWEEP if dim == 1 else
+                    kgs.KGS_KERNEL_TILE if dim == 2 and prec == workloads.FP64 else
+                    kgs.KGS_KERNEL_STREAM)
         assert kgs.kgs_get_info(h).kernel == expected
         e0 = kgs.kgs_energy(h)
         kgs.kgs_step(h, steps)
