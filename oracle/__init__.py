@@ -72,8 +72,8 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SOURCE):
         tmp = LIB_PATH + ".tmp"
         subprocess.run(
-            ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-             "-o", tmp, SOURCE, "-lm"],
+            ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+             "-shared", "-o", tmp, SOURCE, "-lm"],
             check=True,
         )
         os.replace(tmp, LIB_PATH)
@@ -102,6 +102,9 @@ def lib():
         L.kgso_checkerboard_order.restype = ctypes.c_int64
         L.kgso_step.argtypes = [_GP, ctypes.c_double, _DP, _DP, _DP, _DP, ctypes.c_int64]
         L.kgso_step.restype = ctypes.c_int
+        L.kgso_step_passes.argtypes = [_GP, ctypes.c_double, _DP, _DP, _DP, _DP, ctypes.c_int64,
+                                       ctypes.c_int32, ctypes.c_int32]
+        L.kgso_step_passes.restype = ctypes.c_int
         L.kgso_energy.argtypes = [_GP, _DP, _DP, _DP, _DP]
         L.kgso_energy.restype = ctypes.c_double
         _lib = L
@@ -197,6 +200,22 @@ def step(grid: Grid, tau: float, s: State, nsteps: int = 1) -> State:
     rc = lib().kgso_step(ctypes.byref(g), tau, *map(_ptr, s.arrays()), nsteps)
     if rc != 0:
         raise RuntimeError(f"kgso_step failed ({rc})")
+    return s
+
+
+def step_passes(grid: Grid, tau: float, s: State, nsteps: int = 1, storage_bits: int = 64,
+                threads: int = 1) -> State:
+    """nsteps checkerboard DP-AVF2 steps written colour pass by colour pass,
+    in place: bitwise equal to step() for storage_bits=64 and any number of
+    OpenMP threads; storage_bits=32 rounds the values to float32 where a
+    float32 state is stored (on entry, after each red pass, after the blue
+    adjoint pass), with float64 arithmetic throughout.  n must be even."""
+    _check(grid, *s.arrays())
+    g = grid._c()
+    rc = lib().kgso_step_passes(ctypes.byref(g), tau, *map(_ptr, s.arrays()), nsteps,
+                                storage_bits, threads)
+    if rc != 0:
+        raise RuntimeError(f"kgso_step_passes failed ({rc})")
     return s
 
 

@@ -292,3 +292,84 @@ double kgso_energy(const kgso_grid *g, const double *P, const double *Q, const d
     for (int a = 0; a < g->dim; ++a) hd *= g->h;
     return hd * (sum + comp);
 }
+
+/* ------------------------------------------------------------------------
+ * The checkerboard step written colour pass by colour pass (sec. 4.2,
+ * Algorithm 3, with the adjoint passes read as (U, V) then Psi):
+ *   red   points: Psi, then (U, V)      DP-AVF half step with tau/2
+ *   blue  points: Psi, then (U, V)
+ *   blue  points: (U, V), then Psi      adjoint half step with tau/2
+ *   red   points: (U, V), then Psi
+ * Points of one colour have no neighbour of that colour, so the points of a
+ * pass may be visited in any order and the result is bitwise that of
+ * kgso_step.  Two options, neither of which changes an operation:
+ *
+ *  - nthreads > 1 splits every pass over that many OpenMP threads (the
+ *    all-cores timing of the oracle); the result is bitwise that of one
+ *    thread.
+ *  - storage_bits = 32 describes a state stored in float32 between passes:
+ *    the values are rounded to float32 (round to nearest even) on entry,
+ *    at the end of every red pass for the red points, and at the end of the
+ *    blue adjoint pass for the blue points, which are exactly the places
+ *    where a float32 state is written back to memory when each colour pass
+ *    is one sweep over the grid and the two blue passes are one.  All
+ *    arithmetic stays in float64.  storage_bits = 64 rounds nothing.
+ * ---------------------------------------------------------------------- */
+static void round_points_f32(double *P, double *Q, double *U, double *V, const int64_t *pts,
+                             int64_t m, int nthreads)
+{
+#pragma omp parallel for schedule(static) num_threads(nthreads) if (nthreads > 1)
+    for (int64_t t = 0; t < m; ++t) {
+        const int64_t idx = pts[t];
+        P[idx] = (double)(float)P[idx];
+        Q[idx] = (double)(float)Q[idx];
+        U[idx] = (double)(float)U[idx];
+        V[idx] = (double)(float)V[idx];
+    }
+}
+
+static void colour_pass(const kgso_grid *g, double tau_half, const uv_inverse *inv, double *P,
+                        double *Q, double *U, double *V, const int64_t *pts, int64_t m,
+                        int adjoint, int nthreads)
+{
+#pragma omp parallel for schedule(static) num_threads(nthreads) if (nthreads > 1)
+    for (int64_t t = 0; t < m; ++t) {
+        const int64_t idx = pts[t];
+        if (adjoint) {
+            uv_update(g, tau_half, inv, P, Q, U, V, idx);
+            kgso_psi_update(g, tau_half, P, Q, U, idx);
+        } else {
+            kgso_psi_update(g, tau_half, P, Q, U, idx);
+            uv_update(g, tau_half, inv, P, Q, U, V, idx);
+        }
+    }
+}
+
+int kgso_step_passes(const kgso_grid *g, double tau, double *P, double *Q, double *U, double *V,
+                     int64_t nsteps, int32_t storage_bits, int32_t nthreads)
+{
+    /* odd n: two neighbours share a colour, the passes are not independent */
+    if (!grid_ok(g) || (g->n & 1) || nsteps < 0 || (storage_bits != 32 && storage_bits != 64) ||
+        nthreads < 1)
+        return KGSO_EINVAL;
+    const int64_t m = npoints(g);
+    int64_t *order = (int64_t *)malloc((size_t)m * sizeof(int64_t));
+    if (!order) return KGSO_ENOMEM;
+    kgso_checkerboard_order(g->dim, g->n, order);
+    const int64_t nred = m / 2; /* n even: half of the points are red */
+    const int64_t *red = order, *blue = order + nred;
+    const int f32 = storage_bits == 32;
+    const uv_inverse inv = uv_matrix_inverse(g, tau / 2.0);
+    if (f32) round_points_f32(P, Q, U, V, order, m, nthreads);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        colour_pass(g, tau / 2.0, &inv, P, Q, U, V, red, nred, 0, nthreads);
+        if (f32) round_points_f32(P, Q, U, V, red, nred, nthreads);
+        colour_pass(g, tau / 2.0, &inv, P, Q, U, V, blue, m - nred, 0, nthreads);
+        colour_pass(g, tau / 2.0, &inv, P, Q, U, V, blue, m - nred, 1, nthreads);
+        if (f32) round_points_f32(P, Q, U, V, blue, m - nred, nthreads);
+        colour_pass(g, tau / 2.0, &inv, P, Q, U, V, red, nred, 1, nthreads);
+        if (f32) round_points_f32(P, Q, U, V, red, nred, nthreads);
+    }
+    free(order);
+    return KGSO_OK;
+}

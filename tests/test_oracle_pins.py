@@ -440,3 +440,74 @@ def test_finite_speed_of_propagation_lets_sub_blocks_stand_in_for_the_grid():
         wide = (slice(8, 16),) * 3  # one point closer: the wrap has arrived
         assert any(not np.array_equal(a[wide], b[idx][wide])
                    for a, b in zip(sub.arrays(), full.arrays()))
+
+
+# ---------------------------------------------------------------------------
+# The checkerboard step written colour pass by colour pass (sec. 4.2,
+# Algorithm 3): the same scheme as the generic-order step, bitwise, on one
+# thread and on many (points of one colour are independent), and its
+# float32-storage option as the composition of the pinned half passes with
+# numpy's float32 rounding at the stated places.
+# ---------------------------------------------------------------------------
+def _colour_orders(dim, n):
+    order = oracle.checkerboard_order(dim, n)
+    half = order.size // 2
+    assert all(oracle.is_red(dim, n, int(i)) for i in order[:half])
+    return order[:half], order[half:]
+
+
+@pytest.mark.parametrize("dim,n", [(1, 34), (2, 10), (3, 6)])
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_colour_passes_equal_the_checkerboard_step_bitwise(dim, n, threads):
+    rng = np.random.default_rng(900 + 10 * dim + threads)
+    grid = Grid(dim, n, -2.0, 3.0, *rng.uniform(0.5, 2.0, 4))
+    s0 = rand_state(rng, grid.shape, 0.7)
+    a = oracle.step(grid, 0.05, s0.copy(), 4)
+    b = oracle.step_passes(grid, 0.05, s0.copy(), 4, storage_bits=64, threads=threads)
+    for x, y in zip(a.arrays(), b.arrays()):
+        assert np.array_equal(x, y)
+
+
+def _f32(s, pts=None):
+    for f in s.arrays():
+        flat = f.reshape(-1)
+        idx = slice(None) if pts is None else pts
+        flat[idx] = flat[idx].astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("dim,n", [(1, 34), (2, 10), (3, 6)])
+def test_float32_storage_rounds_where_the_state_is_stored(dim, n):
+    rng = np.random.default_rng(950 + dim)
+    grid = Grid(dim, n, -2.0, 3.0, *rng.uniform(0.5, 2.0, 4))
+    tau = 0.05
+    s0 = rand_state(rng, grid.shape, 0.7)
+    red, blue = _colour_orders(dim, n)
+    ref = s0.copy()
+    _f32(ref)
+    for _ in range(3):
+        oracle.base_half(grid, tau / 2, ref, red)
+        _f32(ref, red)
+        oracle.base_half(grid, tau / 2, ref, blue)
+        oracle.adjoint_half(grid, tau / 2, ref, blue)
+        _f32(ref, blue)
+        oracle.adjoint_half(grid, tau / 2, ref, red)
+        _f32(ref, red)
+    for threads in (1, 4):
+        got = oracle.step_passes(grid, tau, s0.copy(), 3, storage_bits=32, threads=threads)
+        for x, y in zip(got.arrays(), ref.arrays()):
+            assert np.array_equal(x, y)
+    # every stored value is a float32 number, and the state differs from the
+    # float64 run only by the storage roundings (a few float32 ulps here)
+    for f in got.arrays():
+        assert np.array_equal(f, f.astype(np.float32).astype(np.float64))
+    exact = oracle.step(grid, tau, s0.copy(), 3)
+    for x, y in zip(got.arrays(), exact.arrays()):
+        err = np.max(np.abs(x - y)) / np.max(np.abs(y))
+        assert 1e-9 < err < 1e-5
+
+
+def test_colour_passes_reject_odd_n():
+    grid = Grid(2, 7, 0.0, 1.0)
+    s = rand_state(np.random.default_rng(1), grid.shape)
+    with pytest.raises(RuntimeError):
+        oracle.step_passes(grid, 0.01, s, 1)
