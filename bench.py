@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--round-work", type=int, default=0,
                     help="serving: point-steps per big-grid round (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=6,
+    ap.add_argument("--cpu-steps", type=int, default=4,
                     help="oracle steps on the full grid for the CPU baseline")
     return ap.parse_args()
 
@@ -93,20 +93,46 @@ def measured_traffic(key: str):
             e["write_kib_per_launch"] * e["write_scale"]) * 1024.0
 
 
+def host_threads() -> int:
+    """Threads the all-cores oracle leg uses: the OpenMP setting if there is
+    one, else the CPUs this process may run on, at most 16 (a one-GPU
+    share of the host)."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return min(int(env), 16)
+    try:
+        return min(len(os.sched_getaffinity(0)), 16)
+    except AttributeError:
+        return min(os.cpu_count() or 1, 16)
+
+
 def cpu_baseline(problem, steps):
-    """The FP64 oracle, single-threaded, on `steps` steps of the same grid."""
+    """The float64 oracle on `steps` steps of the same grid and initial data,
+    once on all host threads (OpenMP over the points of each colour pass) and
+    once on one thread; the two final states must be bitwise equal."""
+    import numpy as np
+
     import oracle
 
     g = oracle.Grid(problem.dim, problem.n, problem.lo, problem.hi, problem.kappa1,
                     problem.kappa2, problem.mu, problem.gamma)
-    s = oracle.State.from_fields(problem.psi, problem.u, problem.v)
-    t0 = time.perf_counter()
-    oracle.step(g, problem.tau, s, steps)
-    dt = time.perf_counter() - t0
+    threads = host_threads()
+    runs = {}
+    for nt in (threads, 1):
+        s = oracle.State.from_fields(problem.psi, problem.u, problem.v)
+        t0 = time.perf_counter()
+        oracle.step_passes(g, problem.tau, s, steps, storage_bits=64, threads=nt)
+        runs[nt] = (time.perf_counter() - t0, s)
+    dt, s_all = runs[threads]
+    dt1, s_one = runs[1]
+    same = all(np.array_equal(a, b) for a, b in zip(s_all.arrays(), s_one.arrays()))
     return {"value": problem.points * steps / dt, "unit": "lattice-point updates/s",
-            "cores": 1, "kind": "oracle",
+            "cores": threads, "kind": "oracle",
             "sample": f"{problem.dim}-D n={problem.n} same initial data, {steps} DP-AVF2 steps "
-                      f"of the full grid, float64, {dt:.1f} s",
+                      f"of the full grid, float64, {dt:.1f} s on {threads} threads "
+                      f"(one thread: {dt1:.1f} s)",
+            "single_core": {"value": problem.points * steps / dt1, "cores": 1},
+            "bitwise_equal_to_single_core": same,
             "host_cpu": host_cpu(), "host_threads": os.cpu_count()}
 
 
@@ -123,18 +149,20 @@ def host_cpu() -> str:
 
 def rel_errors(got, ref):
     """Max-norm relative errors (psi, u, v) of a state against a reference
-    state (numpy arrays or torch tensors); v is scaled by max(|v|, |u|)."""
+    state (numpy arrays or torch tensors), each field against its own
+    largest magnitude; v also against the larger of the v and u scales."""
     def mx(a):
         return float(abs(a).max())
     (gp, gu, gv), (rp, ru, rv) = got, ref
     return {"psi": mx(gp - rp) / max(mx(rp), 1e-300), "u": mx(gu - ru) / max(mx(ru), 1e-300),
-            "v": mx(gv - rv) / max(mx(rv), mx(ru), 1e-300)}
+            "v": mx(gv - rv) / max(mx(rv), 1e-300),
+            "v_uv_scale": mx(gv - rv) / max(mx(rv), mx(ru), 1e-300)}
 
 
 def fp32_vs_fp64(kgs, problems, states, steps):
     """Errors of float32-state results against the float64 path on the same
     problems (the float64 path matches the float64 oracle to 1e-12)."""
-    worst = {"psi": 0.0, "u": 0.0, "v": 0.0}
+    worst = {"psi": 0.0, "u": 0.0, "v": 0.0, "v_uv_scale": 0.0}
     for p, got in zip(problems, states):
         p64 = p.with_(precision=0)
         sim = kgs.simulation_from_problem(p64)
@@ -163,6 +191,26 @@ def device_copy_gbs(torch, stream, mib):
     n = a.numel() * 8
     del a, b
     return 2 * n / best / 1e9
+
+
+def settle_clock(torch, stream, call, min_s=0.3, max_calls=60, tol=0.02):
+    """Untimed repetitions of `call` (one K-step call) until the GPU runs at
+    its steady clock: at least `min_s` seconds of calls, and the last two
+    within `tol` of each other.  Returns what it ran."""
+    times = []
+    t0 = time.perf_counter()
+    while len(times) < max_calls:
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        call()
+        b.record(stream)
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+        if (time.perf_counter() - t0 >= min_s and len(times) >= 2 and
+                abs(times[-1] - times[-2]) <= tol * times[-1]):
+            break
+    return {"calls": len(times), "first_ms": times[0], "last_ms": times[-1],
+            "s": time.perf_counter() - t0}
 
 
 def _timed_ms(torch, stream, fn):
@@ -339,7 +387,7 @@ def bench_serving(args):
             # results in the mix equal results alone (a sample of small requests)
             small = [(rid, j) for rid, j in ids if reqs[j].problem.points <= 1 << 16][:6]
             ok = True
-            fp32_err = {"psi": 0.0, "u": 0.0, "v": 0.0}
+            fp32_err = {"psi": 0.0, "u": 0.0, "v": 0.0, "v_uv_scale": 0.0}
             for rid, j in small:
                 p = reqs[j].problem
                 got = srv.result(rid)
@@ -548,6 +596,7 @@ def main():
     tun = sim.tuning
     sim.step(args.warmup)
     sim.sync()
+    settle = settle_clock(torch, stream, lambda: sim.step(args.steps))
     e0 = sim.energy()
 
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -594,10 +643,15 @@ def main():
     value = updates / wall
     n_dom = int(round(args.steps / spl * per))
     avg_launch_s = max(kernel_ms - closing_ms, 1e-9) / 1e3 / n_dom
-    # algorithmic bytes of one launch: a streaming launch advances every point
-    # by spl steps; a sweep advances half of the points by one step
-    algo_per_launch = ALGO_BYTES[args.precision] * p.points * (spl if per == 1 else 0.5)
+    # algorithmic bytes of one launch at 64/K bytes per point-step (float64;
+    # 32/K in float32) for K steps fused in the launch: a streaming launch
+    # reads and writes every point's four values once, whatever its K; a
+    # sweep launch does so for the half of the points of its colour
+    algo_per_launch = ALGO_BYTES[args.precision] * p.points * (1.0 if per == 1 else 0.5)
     achieved = algo_per_launch / avg_launch_s / 1e9
+    # the same launch priced as if each of its steps moved the state once
+    # (one step per launch); above the peak whenever K > 1 pays off
+    effective = algo_per_launch * (spl if per == 1 else 1) / avg_launch_s / 1e9
     key = f"{args.precision}:" + ("stream%d" % spl if per == 1 else "sweep")
     traffic = measured_traffic(key) if args.n == 256 else None
     out = {
@@ -622,7 +676,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": key, "avg_launch_us": avg_launch_s * 1e6,
-                     "algorithmic_bytes_per_launch": algo_per_launch},
+                     "algorithmic_bytes_per_launch": algo_per_launch,
+                     "steps_per_launch": spl if per == 1 else 0.5,
+                     "effective_GBs": effective, "effective_frac": effective / HBM_PEAK_GBS},
+        "settle": settle,
         "energy_rel_drift": abs(e1 - e0) / abs(e0),
         "kernel_ms": kernel_ms,
         "repeats_ms": reps,

@@ -150,20 +150,21 @@ kgs::Geometry make_geometry(const kgs_config &c)
     return g;
 }
 
-// Library default for a grid, from measurements on MI355X:
+// Library default for a grid, from measurements on MI355X (the branches
+// below, in order):
 //  * the resident kernel when the grid fits one workgroup (small grids are
 //    bound by launch latency otherwise);
-//  * for 3-D float64 grids with n >= 96, the z-streaming kernel with two
-//    steps per launch and 16x16 tiles, the chunk of z-planes the longest
-//    power of two (8..128) that still gives about 200 workgroups (256^3:
-//    chunk 128, 9.9e10 updates/s vs 4.7e10 for one sweep per launch; 128^3:
-//    chunk 16, 9.1e10 vs 5.4e10; smaller n run faster with sweeps);
-//  * for 2-D float64 grids with n >= 512, the 2-D streaming kernel with two
-//    steps per launch and the longest row chunk (8..64) that gives about
-//    1024 waves (1024^2: 7.4e10 updates/s vs 4.2e10 for sweeps; smaller
-//    grids have too few tasks);
-//  * one sweep per launch otherwise (float32 3-D states run fastest that way
-//    at most sizes: 1.2e11 updates/s at 256^3).
+//  * 2-D grids below n = 2048: the tiled kernel, 8x8 tiles with 2 steps per
+//    launch below n = 512, else 4 steps per launch with 16x16 tiles below
+//    n = 1024 and 16x32 (float64) or 32x32 (float32) from there;
+//  * 2-D float64 grids from n = 2048: 16x32 tiles, 4 steps per launch;
+//  * 2-D float32 grids from n = 2048: the y-streaming kernel, 2 steps per
+//    launch, the longest row chunk (8..64) that still gives 8192 waves;
+//  * 3-D grids with n >= 96, both precisions: the z-streaming kernel with
+//    two steps per launch and 16x16 tiles, the chunk of z-planes the longest
+//    power of two (8..128) that still gives about 200 workgroups;
+//  * one colour sweep per launch otherwise (3-D below n = 96, 1-D grids
+//    beyond the resident kernel).
 kgs_tuning default_tuning(const kgs_config &c)
 {
     kgs_tuning t;

@@ -497,7 +497,9 @@ class Server:
     def close(self) -> None:
         if self.handle is not None:
             h, self.handle = self.handle, None
-            lib().kgs_server_free(h)
+            rc = lib().kgs_server_free(h)
+            if rc != KGS_OK:
+                raise KgsError(rc, "kgs_server_free")
 
     def __del__(self):
         try:

@@ -1,11 +1,15 @@
 """GPU: batches of uneven simulations (one batched launch per colour sweep and
-class, optional hipGraph replay) end bitwise where individual runs end."""
+class, optional hipGraph replay) end bitwise where individual runs end, and
+every member matches the oracle (float64 <= 1e-12; float32 as in
+tests/oracle_check.py): points of one colour are independent (sec. 4.2,
+Algorithm 3), so how the members share launches does not change a result."""
 import sys
 
 import numpy as np
 import pytest
 
 from paper_2502_09537_amd import kgs, workloads
+from tests import oracle_check
 
 pytestmark = pytest.mark.gpu
 
@@ -27,6 +31,13 @@ def mixed_problems(seed=0):
 
 def states(sims):
     return [s.read_state() for s in sims]
+
+
+def match_oracle(probs, got, steps, what):
+    steps = [steps] * len(probs) if isinstance(steps, int) else steps
+    for i, (p, g, k) in enumerate(zip(probs, got, steps)):
+        oracle_check.check(p, g, k, label=f"{what} member {i} ({p.dim}-D n={p.n}, {k} steps)",
+                           cache=True)
 
 
 def same(a, b):
@@ -56,6 +67,7 @@ def test_batch_equals_individual_runs_bitwise(graph):
     for s in sims:
         s.close()
     assert same(got, ref)
+    match_oracle(probs, got, 7, f"uniform batch (graph={graph})")
 
 
 def test_graph_replays_match_eager_every_time():
@@ -72,7 +84,9 @@ def test_graph_replays_match_eager_every_time():
         e1 = [s.energy() for s in graphed]
         e0 = [s.energy() for s in eager]
         assert e1 == e0, rep
-        assert same(states(graphed), states(eager)), rep
+        got = states(graphed)
+        assert same(got, states(eager)), rep
+        match_oracle(probs, got, 5 * (rep + 1), f"graph replay {rep}")
     be.close()
     bg.close()
     for s in eager + graphed:
@@ -101,6 +115,7 @@ def test_step_each_uneven_counts():
     for s in sims:
         s.close()
     assert same(got, ref)
+    match_oracle(probs, got, counts, "step_each")
     ref2 = []
     for p, k, k2 in zip(probs, counts, counts2):
         s = kgs.simulation_from_problem(p)
@@ -109,6 +124,7 @@ def test_step_each_uneven_counts():
         ref2.append(s.read_state())
         s.close()
     assert same(got2, ref2)
+    match_oracle(probs, got2, [a + b for a, b in zip(counts, counts2)], "step_each twice")
 
 
 def test_members_stepped_alone_in_between():
@@ -135,6 +151,7 @@ def test_members_stepped_alone_in_between():
         ref.append(s.read_state())
         s.close()
     assert same(got, ref)
+    match_oracle(probs, got, 7, "alone + batched")
 
 
 def test_batch_rejects_bad_input():
@@ -183,6 +200,7 @@ def test_2d_batches_stream_and_equal_individual_runs(graph, prec, sizes):
         for s in sims:
             s.close()
         assert same(got, ref), k_run
+        match_oracle(probs, got, sum(k_run), f"2-D group {k_run} (graph={graph})")
 
 
 def test_2d_members_stepped_alone_between_streamed_batch_runs():
@@ -208,3 +226,4 @@ def test_2d_members_stepped_alone_between_streamed_batch_runs():
         ref.append(s.read_state())
         s.close()
     assert same(got, ref)
+    match_oracle(probs, got, 12, "2-D alone + batched")

@@ -6,13 +6,15 @@ After 200 steps the cone covers the whole grid, so that run is checked by
 properties that hold at any size: the discrete energy is conserved, and the
 symmetric composition is time-reversible (200 steps with -tau return to the
 initial state).  The batched configuration (64 uneven 2-D grids x 500 steps)
-is checked member by member against runs of the same grids alone."""
+is checked member by member against runs of the same grids alone, and its
+members up to n = 256 against the oracle over all 500 steps."""
 import sys
 
 import numpy as np
 import pytest
 
 from paper_2502_09537_amd import kgs, workloads
+from tests import oracle_check
 
 pytestmark = pytest.mark.gpu
 
@@ -57,6 +59,7 @@ def test_batched_config_full_size_equals_runs_alone():
     b.step(500)
     picks = (0, 17, 31, 63)
     got = [sims[i].read_state() for i in picks]
+    small_got = {i: sims[i].read_state() for i, p in enumerate(probs) if p.n <= 256}
     b.close()
     for s in sims:
         s.close()
@@ -67,6 +70,12 @@ def test_batched_config_full_size_equals_runs_alone():
         s.close()
         for x, y in zip(g, ref):
             assert np.array_equal(x, y), i
+    # every member up to n = 256 (the oracle needs about a second each) and
+    # the picks of n <= 512 against the oracle over the whole 500 steps
+    small = [i for i, p in enumerate(probs) if p.n <= 256]
+    say("batched: oracle on", len(small), "members of n <= 256")
+    for i in small:
+        oracle_check.check(probs[i], small_got[i], 500, label=f"member {i} (n={probs[i].n})")
 
 
 @pytest.mark.parametrize("prec", [workloads.FP64, workloads.FP32])
@@ -99,18 +108,28 @@ def test_3d_256_sampled_points_match_the_oracle(prec):
                                               for _ in range(4)]
     for st in starts:
         idx = np.ix_(*[(np.arange(B) + s) % p.n for s in st])
-        s0 = oracle.State.from_fields(p.psi[idx], p.u[idx], p.v[idx])
         g = oracle.Grid(3, B, 0.0, B * h, p.kappa1, p.kappa2, p.mu, p.gamma)
-        oracle.step(g, p.tau, s0, steps)
         c = (slice(lo_i, hi_i),) * 3
-        ref = {"psi": s0.psi[c], "u": s0.U[c], "v": s0.V[c]}
-        got = {"psi": psi[idx][c], "u": u[idx][c], "v": v[idx][c]}
-        scale = {"psi": float(np.max(np.abs(ref["psi"]))), "u": float(np.max(np.abs(ref["u"]))),
-                 "v": max(float(np.max(np.abs(ref["v"]))), float(np.max(np.abs(ref["u"]))))}
-        errs = {k: float(np.max(np.abs(got[k] - ref[k]))) / scale[k] for k in ref}
-        print("  block at", st, errs, flush=True)
-        tol = 1e-12 if prec == workloads.FP64 else 1e-5
-        assert max(errs.values()) <= tol, (st, errs)
+        refs = sub_block_refs(g, p.tau, steps, prec, (p.psi[idx], p.u[idx], p.v[idx]), c)
+        got = (psi[idx][c], u[idx][c], v[idx][c])
+        oracle_check.compare(prec, got, *refs, label=f"block at {st}")
+
+
+def sub_block_refs(g, tau, steps, prec, initial, c):
+    """The float64 oracle (and, for a float32 state, its float32-storage
+    mode) on a periodic sub-block from `initial` = (psi, u, v), restricted to
+    the central points c where the sub-block is exact."""
+    import oracle
+
+    out = []
+    for bits in ((64,) if prec == workloads.FP64 else (64, 32)):
+        s0 = oracle.State.from_fields(*initial)
+        if bits == 64:
+            oracle.step(g, tau, s0, steps)
+        else:
+            oracle.step_passes(g, tau, s0, steps, storage_bits=32)
+        out.append((s0.psi[c], s0.U[c], s0.V[c]))
+    return out + [None] * (2 - len(out))
 
 
 @pytest.mark.parametrize("prec", [workloads.FP64, workloads.FP32])
@@ -166,16 +185,10 @@ def test_largest_grids_sampled_points_match_the_oracle(dim, n, prec):
     hgrid = (hi - lo) / n
     g = oracle.Grid(dim, B, 0.0, B * hgrid, 1.0, 1.0, 1.0, 1.0)
     c = (slice(lo_i, hi_i),) * dim
-    tol = 1e-12 if prec == workloads.FP64 else 1e-5
     for st, ix, (P0, Q0, U0, V0) in zip(starts, index, initial):
-        s0 = oracle.State(P0, Q0, U0, V0)
-        oracle.step(g, tau, s0, steps)
-        got = [block(o, ix)[c] for o in out]
-        ref = [a[c] for a in s0.arrays()]
-        scale = max(float(np.max(np.abs(a))) for a in ref)
-        err = max(float(np.max(np.abs(x - y))) for x, y in zip(got, ref)) / scale
-        print("  block at", st, err, flush=True)
-        assert err <= tol, (st, err)
+        refs = sub_block_refs(g, tau, steps, prec, (P0 + 1j * Q0, U0, V0), c)
+        P, Q, U, V = (block(o, ix)[c] for o in out)
+        oracle_check.compare(prec, (P + 1j * Q, U, V), *refs, label=f"block at {st}")
 
 
 @pytest.mark.parametrize("which,n", [("2d", 2048), ("3d", 256)])

@@ -7,8 +7,8 @@ import sys
 import numpy as np
 import pytest
 
-import oracle
 from paper_2502_09537_amd import kgs, workloads
+from tests import oracle_check
 
 pytestmark = pytest.mark.gpu
 
@@ -82,12 +82,7 @@ def test_resident_is_default_for_small_grids_and_matches_oracle():
     p = workloads.random_problem(2, 24, seed=5, tau=0.02, amp=0.5)
     say("resident 2-D vs oracle")
     ((psi, u, v), _) = run(p, [30], kgs.KGS_KERNEL_RESIDENT)
-    ref = oracle.State.from_fields(p.psi, p.u, p.v)
-    oracle.step(oracle.Grid(p.dim, p.n, p.lo, p.hi, p.kappa1, p.kappa2, p.mu, p.gamma), p.tau,
-                ref, 30)
-    scale = max(np.max(np.abs(f)) for f in ref.arrays())
-    for x, y in zip((psi.real, psi.imag, u, v), ref.arrays()):
-        assert np.max(np.abs(x - y)) <= 1e-12 * scale
+    oracle_check.check(p, (psi, u, v), 30)
 
 
 def test_resident_rejects_grids_that_do_not_fit():
@@ -125,6 +120,8 @@ def test_batch_with_resident_and_sweep_members(graph):
     for g, r in zip(got, ref):
         for x, y in zip(g, r):
             assert np.array_equal(x, y)
+    for i, (p, g) in enumerate(zip(probs, got)):
+        oracle_check.check(p, g, 9, label=f"member {i} (graph={graph})", cache=True)
 
 
 def test_batch_step_each_with_resident_members():
@@ -150,3 +147,5 @@ def test_batch_step_each_with_resident_members():
     for g, r in zip(got, ref):
         for x, y in zip(g, r):
             assert np.array_equal(x, y)
+    for i, (p, g, k) in enumerate(zip(probs, got, steps)):
+        oracle_check.check(p, g, 2 * k, label=f"member {i}")

@@ -8,8 +8,8 @@ import sys
 import numpy as np
 import pytest
 
-import oracle
 from paper_2502_09537_amd import kgs, workloads
+from tests import oracle_check
 
 pytestmark = pytest.mark.gpu
 
@@ -62,12 +62,7 @@ def test_stream2d_matches_oracle():
     p = workloads.config_2d(n=160, steps=60)
     say("stream2d vs oracle")
     ((psi, u, v), _) = run(p, [p.steps], tuning(kgs.KGS_KERNEL_STREAM, 32, 2))
-    ref = oracle.State.from_fields(p.psi, p.u, p.v)
-    oracle.step(oracle.Grid(2, p.n, p.lo, p.hi, p.kappa1, p.kappa2, p.mu, p.gamma), p.tau, ref,
-                p.steps)
-    scale = max(np.max(np.abs(f)) for f in ref.arrays())
-    for x, y in zip((psi.real, psi.imag, u, v), ref.arrays()):
-        assert np.max(np.abs(x - y)) <= 1e-12 * scale
+    oracle_check.check(p, (psi, u, v), p.steps)
 
 
 def test_stream2d_rejects_bad_shapes():

@@ -6,8 +6,8 @@ import sys
 import numpy as np
 import pytest
 
-import oracle
 from paper_2502_09537_amd import kgs, workloads
+from tests import oracle_check
 
 pytestmark = pytest.mark.gpu
 
@@ -75,12 +75,7 @@ def test_stream_matches_oracle_3d_config_reduced():
     p = workloads.config_3d(n=32, steps=200)
     say("stream vs oracle 32^3 x 200")
     (psi, u, v), e = run(p, p.steps, tuning(16, 17, 32, 2))
-    s = oracle.State.from_fields(p.psi, p.u, p.v)
-    g = oracle.Grid(3, p.n, p.lo, p.hi, p.kappa1, p.kappa2, p.mu, p.gamma)
-    oracle.step(g, p.tau, s, p.steps)
-    assert np.max(np.abs(psi - s.psi)) <= 1e-12 * np.max(np.abs(s.psi))
-    assert np.max(np.abs(u - s.U)) <= 1e-12 * np.max(np.abs(s.U))
-    assert np.max(np.abs(v - s.V)) <= 1e-12 * np.max(np.abs(s.U))
+    oracle_check.check(p, (psi, u, v), p.steps)
 
 
 def test_stream_rejects_bad_shapes():

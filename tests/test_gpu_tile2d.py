@@ -1,4 +1,4 @@
-"""GPU: the 2-D tiled kernel (a tile plus halo of both colours in LDS, 1 or 2
+"""GPU: the 2-D tiled kernel (a tile plus halo of both colours in LDS, 1, 2 or 4
 DP-AVF2 steps per launch, ping-pong buffers) gives bitwise the state of the
 one-sweep-per-launch kernel for tiles that divide the grid, ragged edge
 tiles, tiles wider or taller than the grid, every points-per-thread class,
@@ -8,8 +8,8 @@ import sys
 import numpy as np
 import pytest
 
-import oracle
 from paper_2502_09537_amd import kgs, workloads
+from tests import oracle_check
 
 pytestmark = pytest.mark.gpu
 
@@ -44,11 +44,11 @@ CASES = [
     (2, 1, 1, 2, [3]),          # tile and halo wrap around a 2x2 grid
     (4, 3, 1, 1, [2, 1]),
     (30, 7, 5, 2, [5]),         # ragged in both directions
-    (64, 32, 16, 2, [3, 4]),    # 2 points per thread
+    (64, 32, 16, 2, [3, 4]),    # 256 threads, 2 points each
     (64, 16, 16, 1, [3]),
     (130, 32, 16, 2, [3]),      # odd number of points per row and colour
-    (250, 48, 24, 2, [2, 3]),   # 4 points per thread
-    (256, 40, 32, 2, [5]),      # 8 points per thread
+    (250, 48, 24, 2, [2, 3]),   # 256 threads, 4 points each
+    (256, 40, 32, 2, [5]),      # 1584-point block: 512 threads, 4 points each
     (256, 64, 32, 2, [2]),      # too many points for one workgroup: rejected
     (1024, 32, 16, 2, [3]),
     # 4 steps (8 sweeps) per launch: 8 halo rows, 4 compressed positions
@@ -86,12 +86,7 @@ def test_tile2d_matches_oracle():
     p = workloads.config_2d(n=160, steps=60)
     say("tile2d vs oracle")
     ((psi, u, v), _) = run(p, [p.steps], tuning(kgs.KGS_KERNEL_TILE, 32, 16, 2))
-    ref = oracle.State.from_fields(p.psi, p.u, p.v)
-    oracle.step(oracle.Grid(2, p.n, p.lo, p.hi, p.kappa1, p.kappa2, p.mu, p.gamma), p.tau, ref,
-                p.steps)
-    scale = max(np.max(np.abs(f)) for f in ref.arrays())
-    for x, y in zip((psi.real, psi.imag, u, v), ref.arrays()):
-        assert np.max(np.abs(x - y)) <= 1e-12 * scale
+    oracle_check.check(p, (psi, u, v), p.steps)
 
 
 def test_tile2d_rejects_bad_shapes():
