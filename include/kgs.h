@@ -135,6 +135,40 @@ const char *kgs_last_error(const kgs_sim *sim);
 const char *kgs_status_string(int status);
 
 /* ------------------------------------------------------------------------
+ * Stepping without device allocation.  For callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc.  Not a step of the paper's method: the same
+ * DP-AVF2 steps as kgs_step, on fields the caller owns.
+ *
+ * kgs_step_fields advances psi_re + i psi_im, u, v_t (device arrays of n^dim
+ * float64 in the layout above, distinct and owned by the caller) by nsteps
+ * steps of the grid and scheme of cfg, in place.  It enqueues a scatter into
+ * the colour-split layout, the kernels kgs_step would run, and a gather back
+ * into the four arrays, all on `stream` (a hipStream_t, NULL = the null
+ * stream), and returns without waiting.  The result is bitwise that of
+ * kgs_init + kgs_step + kgs_read_state on a handle with the same cfg (with
+ * KGS_FP32 the fields come back rounded to float32, also for nsteps = 0).
+ *
+ * It calls no hipMalloc, hipFree or other allocating routine.  The working
+ * state lives in a fixed scratch area of KGS_STEP_FIELDS_SCRATCH_BYTES per
+ * device, which each device the library runs on holds until the process
+ * ends.  A grid whose state (32 bytes per point with KGS_FP64, 16 with
+ * KGS_FP32) does not fit is rejected with KGS_ENOMEM before anything is
+ * enqueued; where the state fits but not twice the state, the in-place
+ * kernels run instead of the ping-pong ones (same result).  Calls on one
+ * device share that area: calls that overlap in time on one device (other
+ * streams or threads) race and must not be issued.  Consecutive calls on
+ * one stream are ordered and safe; nothing of an earlier call's contents is
+ * read.  Errors: as kgs_init for cfg, KGS_EINVAL for a NULL array or
+ * nsteps < 0, KGS_ENOMEM as above, KGS_EDEVICE for a runtime failure; the
+ * message is kgs_last_error(NULL).
+ */
+#define KGS_STEP_FIELDS_SCRATCH_BYTES (64LL << 20)
+
+int kgs_step_fields(const kgs_config *cfg, double *psi_re, double *psi_im, double *u,
+                    double *v_t, int64_t nsteps, void *stream);
+
+/* ------------------------------------------------------------------------
  * Launch configuration.  Every configuration computes bitwise the same
  * state (same-colour points are independent, sec. 4.2), so these knobs only
  * change speed.

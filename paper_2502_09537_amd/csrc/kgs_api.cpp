@@ -391,6 +391,55 @@ void apply_default_tuning(kgs_sim *s)
     }
 }
 
+// Checks a requested launch configuration against the handle's grid and
+// fills in what KGS_KERNEL_AUTO leaves open.  `pingpong` tells whether the
+// configuration needs the second state buffer.  Allocates nothing.
+int resolve_tuning(kgs_sim *s, const kgs_tuning &t, kgs_tuning &nt, bool &pingpong)
+{
+    nt = t;
+    pingpong = false;
+    if (nt.reserved[0] || nt.reserved[1]) return fail(s, KGS_EINVAL, "reserved must be 0");
+    if (nt.kernel == KGS_KERNEL_AUTO) {
+        const kgs_tuning dt = default_tuning(s->cfg);
+        nt.kernel = dt.kernel;
+        if (nt.tile_x == 0 && nt.tile_y == 0 && nt.chunk == 0 && nt.steps_per_launch == 0) {
+            nt.tile_x = dt.tile_x;
+            nt.tile_y = dt.tile_y;
+            nt.chunk = dt.chunk;
+            nt.steps_per_launch = dt.steps_per_launch;
+        }
+    }
+    if (nt.block == 0) nt.block = 256;
+    if (nt.block < 64 || nt.block > 1024 || nt.block % 64)
+        return fail(s, KGS_EINVAL, "block must be a multiple of 64 in [64, 1024]");
+    if (nt.kernel == KGS_KERNEL_STREAM) {
+        if (s->cfg.dim == 1) return fail(s, KGS_EINVAL, "the streaming kernels are 2-D and 3-D");
+        if (s->cfg.dim == 2) {
+            if ((nt.steps_per_launch != 1 && nt.steps_per_launch != 2) || nt.chunk < 1 ||
+                kgs::stream2d_tasks(s->geo.n, nt.chunk) < 1)
+                return fail(s, KGS_EINVAL, "chunk/steps do not fit the 2-D streaming kernel");
+        } else {
+            kgs::StreamShape sh = {nt.tile_x, nt.tile_y, nt.chunk, nt.steps_per_launch};
+            if (!kgs::stream3d_shape_ok(s->geo, sh, static_cast<int>(elem_bytes(s->cfg.precision))))
+                return fail(s, KGS_EINVAL, "tile/chunk/steps do not fit the streaming kernel");
+        }
+        pingpong = true;
+    } else if (nt.kernel == KGS_KERNEL_TILE) {
+        if (s->cfg.dim != 2) return fail(s, KGS_EINVAL, "the tiled kernel is 2-D");
+        if ((nt.steps_per_launch != 1 && nt.steps_per_launch != 2 && nt.steps_per_launch != 4) ||
+            !kgs::tile2d_shape_ok(s->geo, nt.tile_y, nt.tile_x, 2 * nt.steps_per_launch,
+                                  static_cast<int>(elem_bytes(s->cfg.precision))))
+            return fail(s, KGS_EINVAL, "tile/steps do not fit the 2-D tiled kernel");
+        pingpong = true;
+    } else if (nt.kernel == KGS_KERNEL_RESIDENT) {
+        if (!kgs::resident_fits(s->geo.count, static_cast<int>(elem_bytes(s->cfg.precision))))
+            return fail(s, KGS_EINVAL, "the grid does not fit the resident kernel");
+    } else if (nt.kernel != KGS_KERNEL_SWEEP) {
+        return fail(s, KGS_EINVAL, "kernel family not available for this grid");
+    }
+    return KGS_OK;
+}
+
 }  // namespace
 
 namespace kgs {
@@ -457,6 +506,67 @@ void sim_destroy_pooled(kgs_sim *s)
     if (!s) return;
     release(s);
     delete s;
+}
+
+int set_error(int code, const std::string &msg) { return fail(nullptr, code, msg); }
+
+int step_fields_check(const kgs_config *cfg, const double *P, const double *Q, const double *U,
+                      const double *V, int64_t nsteps, int64_t scratch_bytes)
+{
+    std::string msg;
+    const int rc = validate(cfg, msg);
+    if (rc != KGS_OK) return fail(nullptr, rc, msg);
+    if (!P || !Q || !U || !V) return fail(nullptr, KGS_EINVAL, "state array pointer is NULL");
+    if (nsteps < 0) return fail(nullptr, KGS_EINVAL, "nsteps must be >= 0");
+    const int64_t need = state_bytes(*cfg);
+    if (need > scratch_bytes)
+        return fail(nullptr, KGS_ENOMEM,
+                    "the grid's state needs " + std::to_string(need) +
+                        " bytes of device memory; kgs_step_fields has a fixed scratch area of " +
+                        std::to_string(scratch_bytes) + " bytes per device");
+    return KGS_OK;
+}
+
+int step_fields_run(const kgs_config *cfg, double *P, double *Q, double *U, double *V,
+                    int64_t nsteps, hipStream_t stream, void *scratch, int64_t scratch_bytes)
+{
+    // a handle on the stack whose state lives in the scratch area: the
+    // kernels and the launch sequence are those of kgs_step
+    kgs_sim s;
+    s.cfg = *cfg;
+    s.geo = make_geometry(*cfg);
+    s.h = (cfg->hi - cfg->lo) / cfg->n;
+    s.hd = 1.0;
+    for (int a = 0; a < cfg->dim; ++a) s.hd *= s.h;
+    s.coef = half_step_coef(*cfg, s.h);
+    s.stream = stream;
+    s.plane_bytes = static_cast<size_t>(s.geo.stride) * elem_bytes(cfg->precision);
+    const int64_t sb = state_bytes(*cfg);
+    s.state = scratch;
+    if (2 * sb <= scratch_bytes) s.state2 = static_cast<char *>(scratch) + sb;
+    hipError_t e = hipGetDevice(&s.device);
+    if (e != hipSuccess) return set_error(hip_fail(&s, e, "hipGetDevice"), s.err);
+    // the library's default launch configuration, unless it needs a second
+    // state buffer that the scratch area cannot hold
+    kgs_tuning req;
+    std::memset(&req, 0, sizeof(req));
+    req.kernel = KGS_KERNEL_AUTO;
+    bool pingpong = false;
+    int rc = resolve_tuning(&s, req, s.tuning, pingpong);
+    if (rc != KGS_OK || (pingpong && !s.state2)) {
+        std::memset(&s.tuning, 0, sizeof(s.tuning));
+        s.tuning.block = 256;
+        s.tuning.kernel = kgs::resident_fits(s.geo.count, static_cast<int>(elem_bytes(cfg->precision)))
+                              ? KGS_KERNEL_RESIDENT
+                              : KGS_KERNEL_SWEEP;
+    }
+    e = kgs::launch_scatter(s.geo, cfg->precision, s.state, P, Q, U, V, stream);
+    if (e != hipSuccess) return set_error(hip_fail(&s, e, "scatter kernel"), s.err);
+    rc = kgs_step(&s, nsteps);
+    if (rc != KGS_OK) return set_error(rc, s.err);
+    e = kgs::launch_gather(s.geo, cfg->precision, s.state, P, Q, U, V, stream);
+    if (e != hipSuccess) return set_error(hip_fail(&s, e, "gather kernel"), s.err);
+    return KGS_OK;
 }
 
 }  // namespace kgs
@@ -689,47 +799,13 @@ int kgs_get_tuning(const kgs_sim *s, kgs_tuning *out)
 int kgs_set_tuning(kgs_sim *s, const kgs_tuning *t)
 {
     if (!s || !t) return fail(s, KGS_EINVAL, "handle or tuning is NULL");
-    kgs_tuning nt = *t;
-    if (nt.reserved[0] || nt.reserved[1]) return fail(s, KGS_EINVAL, "reserved must be 0");
-    if (nt.kernel == KGS_KERNEL_AUTO) {
-        const kgs_tuning dt = default_tuning(s->cfg);
-        nt.kernel = dt.kernel;
-        if (nt.tile_x == 0 && nt.tile_y == 0 && nt.chunk == 0 && nt.steps_per_launch == 0) {
-            nt.tile_x = dt.tile_x;
-            nt.tile_y = dt.tile_y;
-            nt.chunk = dt.chunk;
-            nt.steps_per_launch = dt.steps_per_launch;
-        }
-    }
-    if (nt.block == 0) nt.block = 256;
-    if (nt.block < 64 || nt.block > 1024 || nt.block % 64)
-        return fail(s, KGS_EINVAL, "block must be a multiple of 64 in [64, 1024]");
-    if (nt.kernel == KGS_KERNEL_STREAM) {
-        if (s->cfg.dim == 1) return fail(s, KGS_EINVAL, "the streaming kernels are 2-D and 3-D");
-        if (s->cfg.dim == 2) {
-            if ((nt.steps_per_launch != 1 && nt.steps_per_launch != 2) || nt.chunk < 1 ||
-                kgs::stream2d_tasks(s->geo.n, nt.chunk) < 1)
-                return fail(s, KGS_EINVAL, "chunk/steps do not fit the 2-D streaming kernel");
-        } else {
-            kgs::StreamShape sh = {nt.tile_x, nt.tile_y, nt.chunk, nt.steps_per_launch};
-            if (!kgs::stream3d_shape_ok(s->geo, sh, static_cast<int>(elem_bytes(s->cfg.precision))))
-                return fail(s, KGS_EINVAL, "tile/chunk/steps do not fit the streaming kernel");
-        }
-        const int rc = kgs::sim_ensure_state2(s);
+    kgs_tuning nt;
+    bool pingpong = false;
+    int rc = resolve_tuning(s, *t, nt, pingpong);
+    if (rc != KGS_OK) return rc;
+    if (pingpong) {
+        rc = kgs::sim_ensure_state2(s);
         if (rc != KGS_OK) return rc;
-    } else if (nt.kernel == KGS_KERNEL_TILE) {
-        if (s->cfg.dim != 2) return fail(s, KGS_EINVAL, "the tiled kernel is 2-D");
-        if ((nt.steps_per_launch != 1 && nt.steps_per_launch != 2 && nt.steps_per_launch != 4) ||
-            !kgs::tile2d_shape_ok(s->geo, nt.tile_y, nt.tile_x, 2 * nt.steps_per_launch,
-                                  static_cast<int>(elem_bytes(s->cfg.precision))))
-            return fail(s, KGS_EINVAL, "tile/steps do not fit the 2-D tiled kernel");
-        const int rc = kgs::sim_ensure_state2(s);
-        if (rc != KGS_OK) return rc;
-    } else if (nt.kernel == KGS_KERNEL_RESIDENT) {
-        if (!kgs::resident_fits(s->geo.count, static_cast<int>(elem_bytes(s->cfg.precision))))
-            return fail(s, KGS_EINVAL, "the grid does not fit the resident kernel");
-    } else if (nt.kernel != KGS_KERNEL_SWEEP) {
-        return fail(s, KGS_EINVAL, "kernel family not available for this grid");
     }
     s->tuning = nt;
     return KGS_OK;

@@ -62,5 +62,14 @@ kgs_tuning default_tuning_of(const kgs_config &cfg);
 int sim_ensure_state2(kgs_sim *s);
 // Bytes of one state buffer (8 planes) of a valid cfg.
 int64_t state_bytes(const kgs_config &cfg);
+// Sets the calling thread's last error (kgs_last_error(NULL)); returns code.
+int set_error(int code, const std::string &msg);
+// kgs_step_fields, host side: argument and size checks (nothing touches
+// the device), then scatter, kgs_step's launches and gather on `stream`
+// with the state in `scratch` (device memory of scratch_bytes).
+int step_fields_check(const kgs_config *cfg, const double *P, const double *Q, const double *U,
+                      const double *V, int64_t nsteps, int64_t scratch_bytes);
+int step_fields_run(const kgs_config *cfg, double *P, double *Q, double *U, double *V,
+                    int64_t nsteps, hipStream_t stream, void *scratch, int64_t scratch_bytes);
 
 }  // namespace kgs

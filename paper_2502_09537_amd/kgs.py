@@ -32,7 +32,7 @@ EXPORTS = (
     "kgs_batch_free", "kgs_batch_last_error",
     "kgs_server_create", "kgs_server_submit", "kgs_server_run", "kgs_server_poll",
     "kgs_server_result", "kgs_server_release", "kgs_server_cancel", "kgs_server_stats",
-    "kgs_server_free", "kgs_server_last_error",
+    "kgs_server_free", "kgs_server_last_error", "kgs_step_fields",
 )
 KGS_REQ_QUEUED, KGS_REQ_RUNNING, KGS_REQ_DONE, KGS_REQ_FAILED, KGS_REQ_CANCELLED = range(5)
 
@@ -138,6 +138,8 @@ def lib():
             "kgs_server_stats": ([_VP, P(KgsServerStats)], ctypes.c_int),
             "kgs_server_free": ([_VP], ctypes.c_int),
             "kgs_server_last_error": ([_VP], ctypes.c_char_p),
+            "kgs_step_fields": ([P(KgsConfig), _VP, _VP, _VP, _VP, ctypes.c_int64, _VP],
+                                ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -193,6 +195,19 @@ def kgs_init(cfg: KgsConfig, psi_re: int, psi_im: int, u: int, v_t: int, mem: in
 
 def kgs_step(handle, nsteps: int) -> None:
     _check(lib().kgs_step(handle, int(nsteps)), handle)
+
+
+# scratch area of kgs_step_fields per device (KGS_STEP_FIELDS_SCRATCH_BYTES)
+KGS_STEP_FIELDS_SCRATCH_BYTES = 64 << 20
+
+
+def kgs_step_fields(cfg: KgsConfig, psi_re: int, psi_im: int, u: int, v_t: int, nsteps: int,
+                    stream: int = 0) -> None:
+    """Advance four caller-owned float64 device arrays (data_ptr() integers)
+    in place by nsteps steps, enqueued on `stream`; allocates nothing."""
+    rc = lib().kgs_step_fields(ctypes.byref(cfg), psi_re, psi_im, u, v_t, int(nsteps),
+                               stream or None)
+    _check(rc)
 
 
 def kgs_energy(handle) -> float:

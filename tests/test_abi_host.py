@@ -135,3 +135,20 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
         kgs.last_error(None)
     with pytest.raises(ImportError):
         kgs.kgs_step(None, 1)
+
+
+def test_step_fields_rejects_before_device_use(L):
+    # every check of kgs_step_fields comes before it looks up the device, so
+    # fake pointers are never dereferenced
+    f = kgs.lib().kgs_step_fields
+    assert f(None, 1, 1, 1, 1, 1, None) == kgs.KGS_EINVAL
+    assert f(ctypes.byref(good(n=7)), 1, 1, 1, 1, 1, None) == kgs.KGS_EODDN
+    assert f(ctypes.byref(good()), None, 1, 1, 1, 1, None) == kgs.KGS_EINVAL
+    assert f(ctypes.byref(good()), 1, 1, 1, 1, -1, None) == kgs.KGS_EINVAL
+    # 3-D 130^3 float64: 8 planes of 130^3/2 values exceed the scratch area;
+    # 128^3 float64 fills it exactly, and 164^3 float32 does not fit either
+    assert f(ctypes.byref(good(dim=3, n=130)), 1, 1, 1, 1, 1, None) == kgs.KGS_ENOMEM
+    assert "scratch" in kgs.last_error(None)
+    assert 8 * (128 ** 3 // 2) * 8 == kgs.KGS_STEP_FIELDS_SCRATCH_BYTES
+    assert f(ctypes.byref(good(dim=3, n=164, precision=kgs.KGS_FP32)), 1, 1, 1, 1, 1,
+             None) == kgs.KGS_ENOMEM
