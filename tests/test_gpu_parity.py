@@ -142,6 +142,23 @@ def test_energy_matches_oracle_and_is_conserved():
     assert abs(e1 - e0) <= 1e-12 * abs(e0)
 
 
+@pytest.mark.parametrize("dim,n", [(1, 2), (1, 1030), (2, 2), (2, 6), (2, 64), (2, 1030),
+                                   (3, 2), (3, 4), (3, 34), (3, 96), (3, 130), (3, 256)])
+@pytest.mark.parametrize("prec", [workloads.FP64, workloads.FP32])
+def test_energy_matches_oracle_across_shapes(dim, n, prec):
+    # random fields: every neighbour term matters; ragged column blocks and
+    # plane chunks of the reduction
+    p = workloads.random_problem(dim, n, seed=700 + 10 * dim + n, tau=0.01, amp=0.5,
+                                 precision=prec)
+    say("energy vs oracle", dim, n, "fp32" if prec else "fp64")
+    sim = kgs.simulation_from_problem(p)
+    e = sim.energy()
+    psi, u, v = sim.read_state()  # the stored state (rounded to float32 with fp32)
+    sim.close()
+    ref = oracle.energy(grid_of(p), oracle.State.from_fields(psi, u, v))
+    assert abs(e - ref) <= 1e-13 * abs(ref), (e, ref)
+
+
 def test_energy_conserved_1d_config_10k_steps():
     p = workloads.config_1d()
     say("energy drift 1d 1e4 steps")
