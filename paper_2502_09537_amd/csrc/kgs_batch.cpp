@@ -5,9 +5,10 @@
 // Members small enough for one workgroup form classes of their own that the
 // resident kernel advances through a whole run in a single launch (one
 // workgroup per member).  Uniform runs of 2-D classes use the 2-D streaming
-// kernel: two steps per launch over all members, between each member's two
-// state buffers, with an even number of launches so that every member ends
-// in its own buffer.
+// kernel, and of 3-D classes the z-streaming kernel's member-list launch:
+// two steps per launch over all members, between each member's two state
+// buffers, with an even number of launches so that every member ends in
+// its own buffer.
 #include <algorithm>
 #include <cstring>
 #include <map>
@@ -43,6 +44,10 @@ struct BatchClass {
     // members all below n = 2048: the tiled kernel (tiles of s2_ty rows x
     // s2_tx points of one colour) instead of the y-streaming kernel
     bool s2_tile = false;
+    // 3-D streaming (uniform runs of 3-D sweep classes whose members are all
+    // n >= kStream3dMinN): the same descriptor triple, s2_tasks workgroups
+    // of the z-streaming kernel's member-list launch, chunk s2_chunk
+    bool s3 = false;
     int s2_ty = 0, s2_tx = 0;
 };
 
@@ -80,6 +85,12 @@ int bhip(kgs_batch *b, hipError_t e, const char *what)
 }
 
 thread_local std::string g_batch_err;
+
+// 3-D members stream together when every member has n >= kStream3dMinN
+// (at least one full tile along x); the plane chunk of such a launch is the
+// longest that still gives kStream3dGroupItems workgroups (one per CU).
+constexpr int kStream3dMinN = 32;
+constexpr int64_t kStream3dGroupItems = 256;
 
 // Releases everything the batch holds; the first runtime error, if any.
 hipError_t destroy(kgs_batch *b)
@@ -119,7 +130,7 @@ int refresh_descriptors(kgs_batch *b)
         for (size_t i = 0; i < c.members.size(); ++i) {
             const kgs_sim *m = b->sims[c.members[i]];
             changed |= held(c, i) != m->state;
-            if (c.s2) changed |= c.h_s2[i].out != m->state2;
+            if (c.s2 || c.s3) changed |= c.h_s2[i].out != m->state2;
         }
     if (!changed && b->uploaded) return KGS_OK;
     hipError_t e = hipStreamSynchronize(b->own);
@@ -134,7 +145,7 @@ int refresh_descriptors(kgs_batch *b)
             for (size_t i = 0; i < nm; ++i) c.h_members[i].state = b->sims[c.members[i]]->state;
             e = hipMemcpyAsync(c.d_members, c.h_members, nm * sizeof(kgs::BatchMember),
                                hipMemcpyHostToDevice, b->own);
-            if (e == hipSuccess && c.s2) {
+            if (e == hipSuccess && (c.s2 || c.s3)) {
                 // [first launch | even launches | odd launches]
                 for (size_t i = 0; i < nm; ++i) {
                     const kgs_sim *m = b->sims[c.members[i]];
@@ -170,11 +181,12 @@ hipError_t enqueue_uniform(kgs_batch *b, int64_t nsteps)
                                             b->own);
         if (e != hipSuccess) return e;
     }
-    // 2-D streaming classes: launches of 2 steps, and of 1 step where needed
-    // to keep the number of launches even, then the closing red sweep
+    // 2-D and 3-D streaming classes: launches of 2 steps, and of 1 step
+    // where needed to keep the number of launches even, then the closing red
+    // sweep
     const bool streamed = nsteps >= 2;
     for (auto &c : b->classes) {
-        if (!c.s2 || !streamed) continue;
+        if (!(c.s2 || c.s3) || !streamed) continue;
         // K = 2a + r steps: a launches of 4 sweeps and r of 2, one 4 split
         // into two 2s when that count is odd
         const int64_t a = nsteps / 2, r = nsteps % 2;
@@ -186,11 +198,16 @@ hipError_t enqueue_uniform(kgs_batch *b, int64_t nsteps)
         std::memset(&none, 0, sizeof(none));
         for (size_t i = 0; i < stages.size(); ++i) {
             const kgs::Stream2dMember *list = c.d_s2 + (i == 0 ? 0 : (i % 2 ? 2 * nm : nm));
-            hipError_t e = c.s2_tile ? kgs::launch_tile2d_list(c.precision, stages[i], c.s2_ty,
-                                                               c.s2_tx, none, list, nm, c.s2_tasks,
-                                                               b->own, i == 0 ? 1 : 0)
-                                     : kgs::launch_stream2d(c.precision, stages[i], none, list, nm,
-                                                            c.s2_tasks, b->own);
+            hipError_t e;
+            if (c.s3)
+                e = kgs::launch_stream3d_list(c.precision, stages[i], list, nm, c.s2_tasks, i == 0,
+                                              b->own);
+            else if (c.s2_tile)
+                e = kgs::launch_tile2d_list(c.precision, stages[i], c.s2_ty, c.s2_tx, none, list,
+                                            nm, c.s2_tasks, b->own, i == 0 ? 1 : 0);
+            else
+                e = kgs::launch_stream2d(c.precision, stages[i], none, list, nm, c.s2_tasks,
+                                         b->own);
             if (e != hipSuccess) return e;
         }
         hipError_t e = kgs::launch_batch_sweep(c.dim, c.precision, c.d_members, nm, c.blocks,
@@ -199,7 +216,7 @@ hipError_t enqueue_uniform(kgs_batch *b, int64_t nsteps)
     }
     auto sweep = [&](int kind) {
         for (auto &c : b->classes) {
-            if (c.resident || (c.s2 && streamed)) continue;
+            if (c.resident || ((c.s2 || c.s3) && streamed)) continue;
             hipError_t e = kgs::launch_batch_sweep(c.dim, c.precision, c.d_members,
                                                    static_cast<int>(c.members.size()), c.blocks,
                                                    nullptr, 0, kind, b->own);
@@ -420,6 +437,58 @@ int kgs_batch_create(kgs_sim *const *sims, int32_t count, void *stream, kgs_batc
                     }
                     tb += c.s2_tile ? kgs::tile2d_member_tiles(x->geo.n, c.s2_ty, c.s2_tx)
                                     : kgs::stream2d_tasks(x->geo.n, chunk);
+                }
+                c.s2_tasks = tb;
+            } else if (c.dim == 3) {
+                // 3-D runs of several steps: the z-streaming kernel over all
+                // members in one launch when every member is large enough
+                // for its tile (else batched sweeps), with the longest
+                // plane chunk (8..128) that still gives a workgroup per CU
+                const size_t nm = c.members.size();
+                const int eb = c.precision == KGS_FP64 ? 8 : 4;
+                auto items = [&](int ch) {
+                    int64_t t = 0;
+                    for (size_t i = 0; i < nm; ++i)
+                        t += kgs::stream3d_member_items(b->sims[c.members[i]]->geo.n, ch);
+                    return t;
+                };
+                int chunk = 128;
+                while (chunk > 8 && items(chunk) < kStream3dGroupItems) chunk /= 2;
+                bool ok = items(chunk) <= 0x7fffffff;
+                for (size_t i = 0; i < nm && ok; ++i) {
+                    const kgs_sim *x = b->sims[c.members[i]];
+                    ok = x->geo.n >= kStream3dMinN && kgs::stream3d_list_ok(x->geo, chunk, eb);
+                }
+                if (!ok) continue;
+                for (size_t i = 0; i < nm && code == KGS_OK; ++i)
+                    code = kgs::sim_ensure_state2(b->sims[c.members[i]]);
+                if (code != KGS_OK) {
+                    b->err = "second state buffer for the 3-D streaming kernel";
+                    break;
+                }
+                c.s3 = true;
+                c.s2_chunk = chunk;
+                const size_t s3bytes = 3 * nm * sizeof(kgs::Stream2dMember);
+                if ((e = hipMalloc(reinterpret_cast<void **>(&c.d_s2), s3bytes)) != hipSuccess ||
+                    (e = hipHostMalloc(reinterpret_cast<void **>(&c.h_s2), s3bytes,
+                                       hipHostMallocDefault)) != hipSuccess) {
+                    code = bhip(b, e, "descriptor allocation (3-D streaming)");
+                    break;
+                }
+                int64_t tb = 0;
+                for (size_t i = 0; i < nm; ++i) {
+                    const kgs_sim *x = b->sims[c.members[i]];
+                    for (int v = 0; v < 3; ++v) {
+                        kgs::Stream2dMember &m = c.h_s2[v * nm + i];
+                        std::memset(&m, 0, sizeof(m));
+                        m.stride = x->geo.stride;
+                        m.task_begin = tb;
+                        m.k = x->coef;
+                        m.n = x->geo.n;
+                        m.chunk = chunk;
+                        // in/out/first are set by refresh_descriptors
+                    }
+                    tb += kgs::stream3d_member_items(x->geo.n, chunk);
                 }
                 c.s2_tasks = tb;
             }

@@ -11,10 +11,10 @@
 //   * big lane: every other grid, in rounds.  A round advances the running
 //     requests with the least remaining work (points x steps left) first, up
 //     to round_work point-steps per round and steps_per_round steps per
-//     request: 3-D float64 grids with their own z-streaming kernel, 2-D
-//     grids together in 2-D streaming launches (one task list over all of
-//     them), the rest in one batched launch sequence per (dimension,
-//     precision) with per-request step counts.  Shortest-remaining-work-
+//     request: 3-D grids of the z-streaming kernel together in member-list
+//     launches of that kernel, 2-D grids together in 2-D streaming launches
+//     (one task list over all of them), the rest in one batched launch
+//     sequence per (dimension, precision) with per-request step counts.  Shortest-remaining-work-
 //     first keeps the mean and median latency low when the device is
 //     oversubscribed.
 // The host does not wait for the GPU in steady state: device memory comes
@@ -50,6 +50,9 @@
 namespace {
 
 constexpr int64_t kDefaultRoundWork = int64_t(1) << 31;  // point-steps per big-lane round
+// plane chunk of a 3-D member-list launch: the longest (8..128) that still
+// gives this many workgroups (one per CU)
+constexpr int64_t kStream3dGroupItems = 256;
 constexpr size_t kMaxAhead = 2;                          // rounds queued ahead, per lane
 constexpr int kRingSlots = 16;                           // staging slots per lane
 constexpr int kSlotChunk = 1024;                         // energy slots per allocation
@@ -708,6 +711,78 @@ int run_stream2d(kgs_server *s, int prec, int64_t k, const std::vector<Request *
     return KGS_OK;
 }
 
+// 3-D requests of one precision taking k >= 2 steps this round: the same
+// launch sequence as run_stream2d with the z-streaming kernel's member-list
+// launch over all of them (16x16 tiles, the longest plane chunk that still
+// gives a workgroup per CU), then the closing red sweep as one batched
+// sweep.
+int run_stream3d(kgs_server *s, int prec, int64_t k, const std::vector<Request *> &rs)
+{
+    const int nm = static_cast<int>(rs.size());
+    auto items = [&](int ch) {
+        int64_t t = 0;
+        for (const Request *r : rs) t += kgs::stream3d_member_items(r->sim->geo.n, ch);
+        return t;
+    };
+    int chunk = 128;
+    while (chunk > 8 && items(chunk) < kStream3dGroupItems) chunk /= 2;
+    const size_t s3_bytes = align_up(3 * nm * sizeof(kgs::Stream2dMember), 256);
+    const size_t bm_bytes = align_up(nm * sizeof(kgs::BatchMember), 256);
+    int rc = KGS_OK;
+    Ring::Slot *sl = ring_take(s, LANE_BIG, s3_bytes + bm_bytes, rc);
+    if (!sl) return rc;
+    auto *d = reinterpret_cast<kgs::Stream2dMember *>(sl->h);
+    auto *bm = reinterpret_cast<kgs::BatchMember *>(sl->h + s3_bytes);
+    const int bb = kgs::batch_block();
+    int64_t tb = 0, blocks = 0;
+    for (int i = 0; i < nm; ++i) {
+        const kgs_sim *x = rs[i]->sim;
+        for (int v = 0; v < 3; ++v) {  // [first launch | even | odd]
+            kgs::Stream2dMember &m = d[v * nm + i];
+            std::memset(&m, 0, sizeof(m));
+            m.in = v == 2 ? x->state2 : x->state;
+            m.out = v == 2 ? x->state : x->state2;
+            m.stride = x->geo.stride;
+            m.task_begin = tb;
+            m.k = x->coef;
+            m.n = x->geo.n;
+            m.chunk = chunk;
+            m.first = v == 0 ? 1 : 0;
+        }
+        tb += kgs::stream3d_member_items(x->geo.n, chunk);
+        std::memset(&bm[i], 0, sizeof(bm[i]));
+        bm[i].state = x->state;
+        bm[i].stride = x->geo.stride;
+        bm[i].count = x->geo.count;
+        bm[i].block_begin = blocks;
+        bm[i].k = x->coef;
+        bm[i].n = x->geo.n;
+        blocks += (x->geo.count + bb - 1) / bb;
+    }
+    hipStream_t st = s->lane[LANE_BIG];
+    hipError_t e = hipMemcpyAsync(sl->d, sl->h, s3_bytes + bm_bytes, hipMemcpyHostToDevice, st);
+    const int64_t a = k / 2, r = k % 2, split = (a + r) % 2;
+    std::vector<int> stages(static_cast<size_t>(a - split), 4);
+    for (int64_t i = 0; i < 2 * split + r; ++i) stages.push_back(2);
+    const auto *dd = reinterpret_cast<const kgs::Stream2dMember *>(sl->d);
+    for (size_t i = 0; i < stages.size() && e == hipSuccess; ++i) {
+        const kgs::Stream2dMember *list = dd + (i == 0 ? 0 : (i % 2 ? 2 * nm : nm));
+        e = kgs::launch_stream3d_list(prec, stages[i], list, nm, tb, i == 0, st);
+    }
+    if (e == hipSuccess && blocks > 0x7fffffff) e = hipErrorInvalidValue;
+    if (e == hipSuccess)
+        e = kgs::launch_batch_sweep(3, prec, reinterpret_cast<const kgs::BatchMember *>(sl->d + s3_bytes),
+                                    nm, blocks, nullptr, 0, kgs::PASS_R_ADJ, st);
+    const hipError_t e2 = ring_done(s, LANE_BIG, sl);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess)
+        for (Request *q : rs) {
+            q->status = status_of(e);
+            q->err = std::string("3-D streaming launch: ") + hipGetErrorName(e);
+        }
+    return KGS_OK;
+}
+
 // One round: the requests with the least remaining work first, up to the
 // round's work quantum (at least one request).
 int run_big(kgs_server *s)
@@ -730,10 +805,11 @@ int run_big(kgs_server *s)
         work += r->points * k;
     }
     hipStream_t st = s->lane[LANE_BIG];
-    // 3-D own-kernel grids now; 2-D grids taking >= 2 steps streamed
-    // together by (precision, steps); the rest batched by (dim, precision)
+    // 2-D and 3-D streaming grids taking >= 2 steps streamed together by
+    // (precision, steps); 3-D streaming grids taking 1 step with their own
+    // kernel; the rest batched by (dim, precision)
     std::map<int, std::vector<std::pair<Request *, int64_t>>> cls;
-    std::map<std::pair<int, int64_t>, std::vector<Request *>> s2;
+    std::map<std::pair<int, int64_t>, std::vector<Request *>> s2, s3;
     for (auto &pk : pick) {
         Request *r = pk.first;
         if (pk.second == 0) continue;
@@ -743,6 +819,12 @@ int run_big(kgs_server *s)
                 continue;
             }
             r->sim->err.clear();  // no second buffer: sweeps instead
+        }
+        if (r->cfg.dim == 3 && r->sim->tuning.kernel == KGS_KERNEL_STREAM && pk.second >= 2 &&
+            kgs::stream3d_list_ok(r->sim->geo, 8, r->cfg.precision == KGS_FP64 ? 8 : 4) &&
+            r->sim->state2) {
+            s3[{r->cfg.precision, pk.second}].push_back(r);
+            continue;
         }
         if (r->cfg.dim == 3 && r->sim->tuning.kernel == KGS_KERNEL_STREAM) {
             if (kgs_step(r->sim, pk.second) != KGS_OK) {
@@ -755,6 +837,10 @@ int run_big(kgs_server *s)
     }
     for (auto &kv : s2) {
         const int rc = run_stream2d(s, kv.first.first, kv.first.second, kv.second);
+        if (rc != KGS_OK) return rc;
+    }
+    for (auto &kv : s3) {
+        const int rc = run_stream3d(s, kv.first.first, kv.first.second, kv.second);
         if (rc != KGS_OK) return rc;
     }
     if (!cls.empty()) {

@@ -58,13 +58,15 @@ __device__ __forceinline__ const T *at(const T *base, uint32_t byte_offset)
 template <typename T>
 __device__ __forceinline__ Vals<T> load_col(const T *zb2, int64_t stride, int c, uint32_t colb2)
 {
-    const Pair<T> pq = *reinterpret_cast<const Pair<T> *>(at(pair_plane(zb2, stride, c, PAIR_PQ), colb2));
-    const Pair<T> uv = *reinterpret_cast<const Pair<T> *>(at(pair_plane(zb2, stride, c, PAIR_UV), colb2));
+    const Pair<T> pq = *(const Global<Pair<T>> *)(at(pair_plane(zb2, stride, c, PAIR_PQ), colb2));
+    const Pair<T> uv = *(const Global<Pair<T>> *)(at(pair_plane(zb2, stride, c, PAIR_UV), colb2));
     return Vals<T>{{pq.x, pq.y, uv.x, uv.y}};
 }
 
 // Streaming stores: the next launch reads them back, this one never does,
-// so they need not occupy L2.
+// so they need not occupy L2.  Both helpers address global memory
+// explicitly: state pointers read from member descriptors carry no address
+// space of their own.
 template <typename T>
 __device__ __forceinline__ void store_col(T *zb2, int64_t stride, int c, uint32_t colb2,
                                           const Vals<T> &x)
@@ -74,8 +76,8 @@ __device__ __forceinline__ void store_col(T *zb2, int64_t stride, int c, uint32_
     pq.y = x.f[1];
     uv.x = x.f[2];
     uv.y = x.f[3];
-    __builtin_nontemporal_store(pq, reinterpret_cast<Pair<T> *>(at(pair_plane(zb2, stride, c, PAIR_PQ), colb2)));
-    __builtin_nontemporal_store(uv, reinterpret_cast<Pair<T> *>(at(pair_plane(zb2, stride, c, PAIR_UV), colb2)));
+    __builtin_nontemporal_store(pq, (Global<Pair<T>> *)(at(pair_plane(zb2, stride, c, PAIR_PQ), colb2)));
+    __builtin_nontemporal_store(uv, (Global<Pair<T>> *)(at(pair_plane(zb2, stride, c, PAIR_UV), colb2)));
 }
 
 __device__ __forceinline__ int wrap(int v, int m)
@@ -285,10 +287,13 @@ __device__ __forceinline__ void pipeline_step(Pipe<T, S> &st, const Geo &g, T *l
 
 // TX, TY > 0: tile shape fixed at compile time (LDS offsets become
 // immediates); 0: taken from the arguments.
+// One work item (a tile of the grid and a chunk of its z-planes) of a
+// launch; `item` counts the tiles first, then the chunks.
 template <typename T, int S, bool FIRST, int TX, int TY>
-__global__ void __launch_bounds__((max_threads<T, S, TX, TY>()))
-stream3d_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t stride, int n,
-                int tiles_x, int tiles_y, int tile_x_arg, int tile_y_arg, int chunk_len, Coef k)
+__device__ __forceinline__ void stream3d_item(const T *__restrict__ in, T *__restrict__ out,
+                                              int64_t stride, int n, int tiles_x, int tiles_y,
+                                              int tile_x_arg, int tile_y_arg, int chunk_len,
+                                              int item, const Coef &k)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *lds = reinterpret_cast<T *>(lds_raw);
@@ -312,10 +317,6 @@ stream3d_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t stride, i
     int ltx = 0, lty = 0;
     if (g.live) ring_position<S>(tid, tile_x, tile_y, ltx, lty);
 
-    // work item: XCD-aware (consecutive items run on the same XCD)
-    const int G = gridDim.x;
-    int item = blockIdx.x;
-    if ((G & 7) == 0) item = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
     const int ntiles = tiles_x * tiles_y;
     const int tile = item % ntiles;
     const int chunk = item / ntiles;
@@ -374,6 +375,50 @@ stream3d_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t stride, i
     }
 }
 
+// Work item of workgroup blockIdx.x, XCD-aware: the workgroups of a launch
+// are dealt to the 8 XCDs in turn, so consecutive items (neighbouring tiles,
+// which share halo loads) are given to workgroups on the same XCD.
+__device__ __forceinline__ int xcd_item()
+{
+    const int G = gridDim.x;
+    int item = blockIdx.x;
+    if ((G & 7) == 0) item = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+    return item;
+}
+
+template <typename T, int S, bool FIRST, int TX, int TY>
+__global__ void __launch_bounds__((max_threads<T, S, TX, TY>()))
+stream3d_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t stride, int n,
+                int tiles_x, int tiles_y, int tile_x_arg, int tile_y_arg, int chunk_len, Coef k)
+{
+    stream3d_item<T, S, FIRST, TX, TY>(in, out, stride, n, tiles_x, tiles_y, tile_x_arg,
+                                       tile_y_arg, chunk_len, xcd_item(), k);
+}
+
+// Several grids in one launch: member m owns the items [list[m].task_begin,
+// list[m + 1].task_begin) of the launch, each grid with its own state
+// buffers, constants, size and chunk, all with the compiled-in TX x TY
+// tile.
+template <typename T, int S, bool FIRST, int TX, int TY>
+__global__ void __launch_bounds__((max_threads<T, S, TX, TY>()))
+stream3d_list_kernel(const Stream2dMember *__restrict__ list, int nm)
+{
+    const int item = xcd_item();
+    int lo = 0, hi = nm - 1;  // last member whose first item is <= item
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (list[mid].task_begin <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    const Stream2dMember &m = list[lo];
+    const int n = m.n;
+    const Coef k = m.k;
+    const int tiles_x = ((n >> 1) + TX - 1) / TX, tiles_y = (n + TY - 1) / TY;
+    stream3d_item<T, S, FIRST, TX, TY>(static_cast<const T *>(m.in), static_cast<T *>(m.out),
+                                       m.stride, n, tiles_x, tiles_y, TX, TY, m.chunk,
+                                       item - static_cast<int>(m.task_begin), k);
+}
+
 template <typename T, int S>
 hipError_t launch_typed(const Geometry &g, const StreamShape &sh, const T *in, T *out, bool first,
                         const Coef &k, hipStream_t s)
@@ -408,7 +453,55 @@ hipError_t launch_typed(const Geometry &g, const StreamShape &sh, const T *in, T
     return hipGetLastError();
 }
 
+// Launches over member lists use the 16x16 tile, compiled in.
+constexpr int kListTile = 16;
+
+template <typename T, int S>
+hipError_t launch_list_typed(const Stream2dMember *list, int nm, int64_t items, bool first,
+                             hipStream_t s)
+{
+    constexpr int TX = kListTile, TY = kListTile;
+    constexpr int BX = TX + 2 * ((S + 1) / 2), BY = TY + 2 * S;
+    constexpr int threads = (BX * BY + 63) / 64 * 64;
+    const size_t lds = static_cast<size_t>(2) * S * 3 * lds_plane(BX, BY) * sizeof(T);
+    auto kern = first ? stream3d_list_kernel<T, S, true, TX, TY>
+                      : stream3d_list_kernel<T, S, false, TX, TY>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(items)), dim3(threads), lds, s, list, nm);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+int stream3d_list_tile() { return kListTile; }
+
+int64_t stream3d_member_items(int n, int chunk)
+{
+    const int64_t tx = (n / 2 + kListTile - 1) / kListTile, ty = (n + kListTile - 1) / kListTile;
+    return tx * ty * ((n + chunk - 1) / chunk);
+}
+
+bool stream3d_list_ok(const Geometry &g, int chunk, int elem_bytes)
+{
+    const StreamShape sh = {kListTile, kListTile, chunk, 2};
+    return stream3d_shape_ok(g, sh, elem_bytes);
+}
+
+hipError_t launch_stream3d_list(int precision, int stages, const Stream2dMember *list, int nm,
+                                int64_t total_items, bool first, hipStream_t s)
+{
+    if (!list || nm < 1 || total_items < 1 || total_items > 0x7fffffff ||
+        (stages != 2 && stages != 4))
+        return hipErrorInvalidValue;
+    if (precision == 0)
+        return stages == 2 ? launch_list_typed<double, 2>(list, nm, total_items, first, s)
+                           : launch_list_typed<double, 4>(list, nm, total_items, first, s);
+    return stages == 2 ? launch_list_typed<float, 2>(list, nm, total_items, first, s)
+                       : launch_list_typed<float, 4>(list, nm, total_items, first, s);
+}
 
 bool stream3d_shape_ok(const Geometry &g, const StreamShape &sh, int elem_bytes)
 {

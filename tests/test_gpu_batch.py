@@ -227,3 +227,48 @@ def test_2d_members_stepped_alone_between_streamed_batch_runs():
         s.close()
     assert same(got, ref)
     match_oracle(probs, got, 12, "2-D alone + batched")
+
+
+def stream3d_problems(seed=0):
+    # 3-D members all large enough for the z-streaming kernel's member-list
+    # launch (one class per precision), ragged against the 16x16 tile and the
+    # plane chunks
+    specs = [(32, 0), (40, 0), (66, 0), (96, 0), (34, 0), (128, 0), (32, 1), (50, 1), (72, 1)]
+    return [workloads.random_problem(3, n, seed=seed * 100 + i, tau=0.03, amp=0.5, precision=prec)
+            for i, (n, prec) in enumerate(specs)]
+
+
+@pytest.mark.parametrize("graph", [False, True])
+@pytest.mark.parametrize("calls", [(2,), (3,), (4, 5), (7,)])
+def test_batch_3d_streaming_equals_individual_runs_and_oracle(graph, calls):
+    probs = stream3d_problems(4)
+    total = sum(calls)
+    say("3-D streaming batch, graph =", graph, "calls", calls)
+    ref = []
+    for p in probs:
+        s = kgs.simulation_from_problem(p)
+        s.step(total)
+        ref.append(s.read_state())
+        s.close()
+    sims = [kgs.simulation_from_problem(p) for p in probs]
+    b = kgs.Batch(sims, graph=graph)
+    for k in calls:
+        b.step(k)
+    got = states(sims)
+    if graph:
+        # a replay of the captured run on top, against the eager path
+        b.step(calls[0])
+        again = states(sims)
+    b.close()
+    for s in sims:
+        s.close()
+    assert same(got, ref)
+    match_oracle(probs, got, total, f"3-D streaming batch (graph={graph})")
+    if graph:
+        ref2 = []
+        for p in probs:
+            s = kgs.simulation_from_problem(p)
+            s.step(total + calls[0])
+            ref2.append(s.read_state())
+            s.close()
+        assert same(again, ref2)

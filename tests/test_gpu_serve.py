@@ -85,6 +85,33 @@ def test_2d_groups_equal_results_alone(sizes):
     srv.close()
 
 
+def test_3d_streaming_groups_equal_results_alone_and_oracle():
+    # 3-D requests of the z-streaming kernel advanced together in member-list
+    # launches (rounds of 4 steps; the last round of a request takes 1..3:
+    # one step runs the request's own launches), joining at different times
+    specs = [(96, 0, 9), (100, 1, 13), (128, 0, 6), (96, 1, 7), (112, 0, 11)]
+    probs = [workloads.gaussian_problem(3, n, 60 + i, -6.0, 6.0, 0.01, k, precision=prec)
+             for i, (n, prec, k) in enumerate(specs)]
+    say("3-D streaming groups", specs)
+    srv = kgs.Server(budget_bytes=16 << 30, steps_per_round=4)
+    ids = [srv.submit_problem(p) for p in probs[:3]]
+    srv.run(1)
+    ids += [srv.submit_problem(p) for p in probs[3:]]
+    while True:
+        nr, nq = srv.run(1)
+        if nr == 0 and nq == 0:
+            break
+    for rid, p in zip(ids, probs):
+        info = srv.poll(rid)
+        assert info.state == kgs.KGS_REQ_DONE, (rid, info.state, info.status)
+        got = srv.result(rid)
+        ref, e_ref = alone(p, p.steps)
+        assert equal(got, ref), p.n
+        assert info.energy_end == e_ref
+        oracle_check.check(p, got, p.steps, label=f"served 3-D n={p.n}")
+    srv.close()
+
+
 def test_admission_respects_the_budget():
     probs = [workloads.gaussian_problem(2, 128, i, -6.0, 6.0, 0.01, 12) for i in range(6)]
     say("budget")
