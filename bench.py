@@ -193,7 +193,7 @@ def device_copy_gbs(torch, stream, mib):
     return 2 * n / best / 1e9
 
 
-def settle_clock(torch, stream, call, min_s=0.3, max_calls=60, tol=0.02):
+def settle_clock(torch, stream, call, min_s=0.5, max_calls=1000, tol=0.02):
     """Untimed repetitions of `call` (one K-step call) until the GPU runs at
     its steady clock: at least `min_s` seconds of calls, and the last two
     within `tol` of each other.  Returns what it ran."""
