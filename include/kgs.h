@@ -222,9 +222,15 @@ int kgs_set_tuning(kgs_sim *sim, const kgs_tuning *t);
  * `steps` DP-AVF2 steps (the faster of two timings) on the handle's current
  * state, restore the state after every candidate, and keep the fastest.  The
  * state is unchanged on return.  With use_cache != 0 a winner found earlier
- * in this process for the same (dim, n, precision, device) is reused without
- * timing.  Writes the chosen configuration to *best (may be NULL).  Needs
- * one extra copy of the state in device memory while it runs. */
+ * for the same (dim, n, precision, GPU architecture) is reused without
+ * timing: found in this process, or read (once per process and file name)
+ * from the file that the environment variable KGS_TUNE_CACHE names, to
+ * which every winner is appended as one
+ * text line ("kgs-tune-v1 arch dim n precision kernel block tile_x tile_y
+ * chunk steps_per_launch"; the last line for a key wins; lines that do not
+ * parse, or whose configuration no longer fits the grid, are ignored).
+ * Writes the chosen configuration to *best (may be NULL).  Needs one extra
+ * copy of the state in device memory while it runs. */
 int kgs_autotune(kgs_sim *sim, int32_t steps, int32_t use_cache, kgs_tuning *best);
 
 /* Sizes of a handle: bytes of device memory it holds and the name of the

@@ -71,7 +71,8 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("libkgs build failed:\n" + msg)
     tmp = LIB + ".tmp"
     link = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
-            "-L", os.path.join(ROCM, "lib"), "-lamdhip64", "-pthread", "-Wl,--no-undefined"]
+            "-L", os.path.join(ROCM, "lib"), "-lamdhip64", "-lrocprofiler-sdk-roctx", "-pthread",
+            "-Wl,--no-undefined"]
     r = subprocess.run(link, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("libkgs link failed:\n" + " ".join(link) + "\n" + r.stdout + r.stderr)

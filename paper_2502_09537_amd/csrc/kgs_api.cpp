@@ -16,6 +16,7 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include "kgs_trace.h"
 #include "kgs_internal.h"
 #include "kgs_sim.h"
 
@@ -602,6 +603,7 @@ int64_t kgs_required_bytes(const kgs_config *cfg)
 int kgs_init(const kgs_config *cfg, const double *psi_re, const double *psi_im, const double *u,
              const double *v_t, int32_t mem, void *stream, kgs_sim **out)
 {
+    KGS_TRACE("kgs_init");
     if (!out) return fail(nullptr, KGS_EINVAL, "out is NULL");
     *out = nullptr;
     std::string msg;
@@ -629,6 +631,7 @@ int kgs_init(const kgs_config *cfg, const double *psi_re, const double *psi_im, 
 
 int kgs_step(kgs_sim *s, int64_t nsteps)
 {
+    KGS_TRACE("kgs_step");
     if (!s) return fail(nullptr, KGS_EINVAL, "handle is NULL");
     if (nsteps < 0) return fail(s, KGS_EINVAL, "nsteps must be >= 0");
     if (nsteps == 0) return KGS_OK;
@@ -707,6 +710,7 @@ int kgs_step(kgs_sim *s, int64_t nsteps)
 
 int kgs_energy(kgs_sim *s, double *energy)
 {
+    KGS_TRACE("kgs_energy");
     if (!s || !energy) return fail(s, KGS_EINVAL, "handle or output is NULL");
     if (!s->host_out) return fail(s, KGS_EINVAL, "handle belongs to a server");
     int rc = check_device(s);
@@ -726,6 +730,7 @@ int kgs_energy(kgs_sim *s, double *energy)
 
 int kgs_read_state(kgs_sim *s, double *P, double *Q, double *U, double *V, int32_t mem)
 {
+    KGS_TRACE("kgs_read_state");
     if (!s) return fail(nullptr, KGS_EINVAL, "handle is NULL");
     if (!P || !Q || !U || !V) return fail(s, KGS_EINVAL, "state array pointer is NULL");
     if (mem != KGS_HOST && mem != KGS_DEVICE)
@@ -759,6 +764,7 @@ int kgs_read_state(kgs_sim *s, double *P, double *Q, double *U, double *V, int32
 int kgs_write_state(kgs_sim *s, const double *P, const double *Q, const double *U,
                     const double *V, int32_t mem)
 {
+    KGS_TRACE("kgs_write_state");
     if (!s) return fail(nullptr, KGS_EINVAL, "handle is NULL");
     int rc = check_device(s);
     if (rc != KGS_OK) return rc;
@@ -767,6 +773,7 @@ int kgs_write_state(kgs_sim *s, const double *P, const double *Q, const double *
 
 int kgs_sync(kgs_sim *s)
 {
+    KGS_TRACE("kgs_sync");
     if (!s) return fail(nullptr, KGS_EINVAL, "handle is NULL");
     int rc = check_device(s);
     if (rc != KGS_OK) return rc;
@@ -776,6 +783,7 @@ int kgs_sync(kgs_sim *s)
 
 int kgs_free(kgs_sim *s)
 {
+    KGS_TRACE("kgs_free");
     if (!s) return KGS_OK;
     int rc = check_device(s);
     if (rc == KGS_OK) {
@@ -798,6 +806,7 @@ int kgs_get_tuning(const kgs_sim *s, kgs_tuning *out)
 
 int kgs_set_tuning(kgs_sim *s, const kgs_tuning *t)
 {
+    KGS_TRACE("kgs_set_tuning");
     if (!s || !t) return fail(s, KGS_EINVAL, "handle or tuning is NULL");
     kgs_tuning nt;
     bool pingpong = false;

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include "kgs.h"
+#include "kgs_trace.h"
 #include "kgs_internal.h"
 #include "kgs_sim.h"
 
@@ -264,6 +265,7 @@ const char *kgs_batch_last_error(const kgs_batch *b) { return b ? b->err.c_str()
 
 int kgs_batch_create(kgs_sim *const *sims, int32_t count, void *stream, kgs_batch **out)
 {
+    KGS_TRACE("kgs_batch_create");
     if (!out) {
         g_batch_err = "out is NULL";
         return KGS_EINVAL;
@@ -524,6 +526,7 @@ int kgs_batch_set_graph(kgs_batch *b, int32_t enable)
 
 int kgs_batch_step(kgs_batch *b, int64_t nsteps)
 {
+    KGS_TRACE("kgs_batch_step");
     if (!b) return KGS_EINVAL;
     if (nsteps < 0) return bfail(b, KGS_EINVAL, "nsteps must be >= 0");
     if (nsteps == 0) return KGS_OK;
@@ -564,6 +567,7 @@ int kgs_batch_step(kgs_batch *b, int64_t nsteps)
 
 int kgs_batch_step_each(kgs_batch *b, const int64_t *nsteps)
 {
+    KGS_TRACE("kgs_batch_step_each");
     if (!b || !nsteps) return bfail(b, KGS_EINVAL, "batch or nsteps is NULL");
     int64_t kmax = 0;
     for (size_t i = 0; i < b->sims.size(); ++i) {
@@ -670,6 +674,7 @@ int kgs_batch_step_each(kgs_batch *b, const int64_t *nsteps)
 
 int kgs_batch_free(kgs_batch *b)
 {
+    KGS_TRACE("kgs_batch_free");
     if (!b) return KGS_OK;
     int rc = KGS_OK;
     if (hipSetDevice(b->device) != hipSuccess || hipStreamSynchronize(b->own) != hipSuccess)

@@ -130,6 +130,11 @@ struct Stream2dMember {
 // can lower it).
 constexpr int kResidentMaxLds = 160 * 1024;
 
+// Lets `kernel` take `bytes` of dynamic LDS on the current device: one
+// runtime call the first time a kernel needs more than it was allowed, none
+// afterwards (kgs_launch.cpp).
+hipError_t allow_dynamic_lds(const void *kernel, int bytes);
+
 // Kernel launchers (kgs_sweep.hip, kgs_energy.hip, kgs_stream3d.hip).  They check the launch
 // shape against the geometry on the host and return hipErrorInvalidValue
 // rather than launch a kernel whose indexing would not fit.

@@ -11,6 +11,7 @@
 #include <string>
 
 #include "kgs.h"
+#include "kgs_trace.h"
 #include "kgs_sim.h"
 
 namespace {
@@ -50,6 +51,7 @@ int scratch_address(void **out)
 extern "C" int kgs_step_fields(const kgs_config *cfg, double *psi_re, double *psi_im, double *u,
                                double *v_t, int64_t nsteps, void *stream)
 {
+    KGS_TRACE("kgs_step_fields");
     int rc = kgs::step_fields_check(cfg, psi_re, psi_im, u, v_t, nsteps,
                                     KGS_STEP_FIELDS_SCRATCH_BYTES);
     if (rc != KGS_OK) return rc;

@@ -44,6 +44,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include "kgs.h"
+#include "kgs_trace.h"
 #include "kgs_internal.h"
 #include "kgs_sim.h"
 
@@ -995,6 +996,7 @@ const char *kgs_server_last_error(const kgs_server *s) { return s ? s->err.c_str
 
 int kgs_server_create(const kgs_server_config *cfg, void *stream, kgs_server **out)
 {
+    KGS_TRACE("kgs_server_create");
     if (!out) return sfail(nullptr, KGS_EINVAL, "out is NULL");
     *out = nullptr;
     if (!cfg || cfg->budget_bytes <= 0 || cfg->max_active < 0 || cfg->steps_per_round < 0 ||
@@ -1048,6 +1050,7 @@ int kgs_server_submit(kgs_server *s, const kgs_config *cfg, const double *psi_re
                       const double *psi_im, const double *u, const double *v_t, int32_t mem,
                       int64_t nsteps, int64_t *id)
 {
+    KGS_TRACE("kgs_server_submit");
     if (!s || !id) return sfail(s, KGS_EINVAL, "server or id is NULL");
     *id = 0;
     if (!cfg || !psi_re || !psi_im || !u || !v_t) return sfail(s, KGS_EINVAL, "NULL argument");
@@ -1104,6 +1107,7 @@ int kgs_server_submit(kgs_server *s, const kgs_config *cfg, const double *psi_re
 
 int kgs_server_run(kgs_server *s, int32_t rounds, int32_t *n_running, int32_t *n_queued)
 {
+    KGS_TRACE("kgs_server_run");
     if (!s || rounds < 0) return sfail(s, KGS_EINVAL, "bad arguments");
     if (hipSetDevice(s->device) != hipSuccess) return sfail(s, KGS_EDEVICE, "hipSetDevice failed");
     for (int32_t i = 0; i < rounds; ++i) {
@@ -1139,6 +1143,7 @@ int kgs_server_poll(const kgs_server *s, int64_t id, kgs_request_info *info)
 int kgs_server_result(kgs_server *s, int64_t id, double *psi_re, double *psi_im, double *u,
                       double *v_t, int32_t mem)
 {
+    KGS_TRACE("kgs_server_result");
     if (!s) return sfail(nullptr, KGS_EINVAL, "server is NULL");
     auto it = s->reqs.find(id);
     if (it == s->reqs.end()) return sfail(s, KGS_EINVAL, "unknown request");
@@ -1176,6 +1181,7 @@ int kgs_server_release(kgs_server *s, int64_t id)
 
 int kgs_server_cancel(kgs_server *s, int64_t id)
 {
+    KGS_TRACE("kgs_server_cancel");
     if (!s) return KGS_EINVAL;
     auto it = s->reqs.find(id);
     if (it == s->reqs.end()) return sfail(s, KGS_EINVAL, "unknown request");
@@ -1220,6 +1226,7 @@ int kgs_server_stats(const kgs_server *s, kgs_server_stats_t *st)
 
 int kgs_server_free(kgs_server *s)
 {
+    KGS_TRACE("kgs_server_free");
     if (!s) return KGS_OK;
     int rc = KGS_OK;
     if (hipSetDevice(s->device) != hipSuccess) rc = KGS_EDEVICE;

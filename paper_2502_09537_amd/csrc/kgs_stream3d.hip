@@ -444,9 +444,7 @@ hipError_t launch_typed(const Geometry &g, const StreamShape &sh, const T *in, T
         if (sh.tile_x == 16 && sh.tile_y == 16)
             kern = first ? stream3d_kernel<T, S, true, 16, 16> : stream3d_kernel<T, S, false, 16, 16>;
     }
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       static_cast<int>(lds));
+    hipError_t e = allow_dynamic_lds(reinterpret_cast<const void *>(kern), static_cast<int>(lds));
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(items)), dim3(threads), lds, s, in, out,
                        g.stride, g.n, tiles_x, tiles_y, sh.tile_x, sh.tile_y, sh.chunk, k);
@@ -466,9 +464,7 @@ hipError_t launch_list_typed(const Stream2dMember *list, int nm, int64_t items, 
     const size_t lds = static_cast<size_t>(2) * S * 3 * lds_plane(BX, BY) * sizeof(T);
     auto kern = first ? stream3d_list_kernel<T, S, true, TX, TY>
                       : stream3d_list_kernel<T, S, false, TX, TY>;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       static_cast<int>(lds));
+    hipError_t e = allow_dynamic_lds(reinterpret_cast<const void *>(kern), static_cast<int>(lds));
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(items)), dim3(threads), lds, s, list, nm);
     return hipGetLastError();

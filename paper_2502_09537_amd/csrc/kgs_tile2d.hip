@@ -197,9 +197,7 @@ hipError_t launch_ppt(int ty, int txc, bool first, const Stream2dMember &one,
     const int NB = (ty + 2 * HY) * (txc + 2 * HX);
     const size_t lds = static_cast<size_t>(6) * NB * sizeof(T);
     auto kern = first ? tile2d_kernel<T, S, NT, PPT, true> : tile2d_kernel<T, S, NT, PPT, false>;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       static_cast<int>(lds));
+    hipError_t e = allow_dynamic_lds(reinterpret_cast<const void *>(kern), static_cast<int>(lds));
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(tiles)), dim3(NT), lds, s, one, list,
                        nm, ty, txc);

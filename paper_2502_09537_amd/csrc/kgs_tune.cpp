@@ -2,24 +2,87 @@
 // of its current state and keeps the fastest.  Every configuration computes
 // bitwise the same state (same-colour points are independent), so tuning
 // only changes speed; the state is restored after every candidate.  Winners
-// are cached per (dimension, n, precision, device) for the process.
+// are cached per (dimension, n, precision, GPU architecture) for the
+// process and, when the environment variable KGS_TUNE_CACHE names a file,
+// in that file: one line per winner, appended, read back by later calls in
+// any process (the last line for a key wins).
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 #include <vector>
 
 #include <hip/hip_runtime_api.h>
 
 #include "kgs.h"
+#include "kgs_trace.h"
 #include "kgs_internal.h"
 #include "kgs_sim.h"
 
 namespace {
 
-using Key = std::tuple<int, int, int, int>;  // dim, n, precision, device
+using Key = std::tuple<int, int, int, std::string>;  // dim, n, precision, architecture
 std::map<Key, kgs_tuning> g_cache;
 std::mutex g_cache_mutex;
+std::string g_loaded_file;  // the cache file whose lines are in g_cache
+
+constexpr const char *kFileTag = "kgs-tune-v1";
+
+// Architecture name of a device (e.g. gfx950:sramecc+:xnack-), or "" on a
+// runtime error.
+std::string arch_of(int device)
+{
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return std::string();
+    std::string a(prop.gcnArchName);
+    for (char &ch : a)
+        if (ch == ' ') ch = '_';
+    return a;
+}
+
+std::string cache_file()
+{
+    const char *p = std::getenv("KGS_TUNE_CACHE");
+    return p ? std::string(p) : std::string();
+}
+
+// Reads the cache file's lines into g_cache once per file name (caller
+// holds g_cache_mutex).  Lines that do not parse are skipped.
+void load_file_locked(const std::string &path)
+{
+    if (path.empty() || path == g_loaded_file) return;
+    g_loaded_file = path;
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return;
+    char line[512];
+    while (std::fgets(line, sizeof(line), f)) {
+        char tag[32], arch[256];
+        int dim, n, prec;
+        kgs_tuning t;
+        std::memset(&t, 0, sizeof(t));
+        if (std::sscanf(line, "%31s %255s %d %d %d %d %d %d %d %d %d", tag, arch, &dim, &n, &prec,
+                        &t.kernel, &t.block, &t.tile_x, &t.tile_y, &t.chunk,
+                        &t.steps_per_launch) == 11 &&
+            std::strcmp(tag, kFileTag) == 0)
+            g_cache[Key{dim, n, prec, std::string(arch)}] = t;
+    }
+    std::fclose(f);
+}
+
+// Appends a winner to the cache file (caller holds g_cache_mutex).
+void append_file_locked(const std::string &path, const Key &k, const kgs_tuning &t)
+{
+    if (path.empty()) return;
+    FILE *f = std::fopen(path.c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, "%s %s %d %d %d %d %d %d %d %d %d\n", kFileTag, std::get<3>(k).c_str(),
+                 std::get<0>(k), std::get<1>(k), std::get<2>(k), t.kernel, t.block, t.tile_x,
+                 t.tile_y, t.chunk, t.steps_per_launch);
+    std::fclose(f);
+}
 
 std::vector<kgs_tuning> candidates(const kgs_sim *s)
 {
@@ -90,16 +153,20 @@ std::vector<kgs_tuning> candidates(const kgs_sim *s)
 
 extern "C" int kgs_autotune(kgs_sim *s, int32_t steps, int32_t use_cache, kgs_tuning *best)
 {
+    KGS_TRACE("kgs_autotune");
     if (!s || steps < 1) return KGS_EINVAL;
-    const Key key{s->cfg.dim, s->cfg.n, s->cfg.precision, s->device};
+    const Key key{s->cfg.dim, s->cfg.n, s->cfg.precision, arch_of(s->device)};
+    const std::string file = cache_file();
     if (use_cache) {
         std::lock_guard<std::mutex> lock(g_cache_mutex);
+        load_file_locked(file);
         auto it = g_cache.find(key);
-        if (it != g_cache.end()) {
-            int rc = kgs_set_tuning(s, &it->second);
-            if (rc == KGS_OK && best) *best = it->second;
-            return rc;
+        // an entry that no longer fits the grid is tuned again
+        if (it != g_cache.end() && kgs_set_tuning(s, &it->second) == KGS_OK) {
+            if (best) *best = it->second;
+            return KGS_OK;
         }
+        s->err.clear();
     }
     if (hipSetDevice(s->device) != hipSuccess) return KGS_EDEVICE;
     const size_t bytes = 8 * s->plane_bytes;
@@ -161,6 +228,7 @@ extern "C" int kgs_autotune(kgs_sim *s, int32_t steps, int32_t use_cache, kgs_tu
     if (rc == KGS_OK) {
         std::lock_guard<std::mutex> lock(g_cache_mutex);
         g_cache[key] = winner;
+        append_file_locked(file, key, winner);
     }
     if (best) *best = winner;
     return rc;

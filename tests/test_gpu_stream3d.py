@@ -130,3 +130,36 @@ def test_autotune_keeps_state_and_results():
             again.block) == (best.kernel, best.tile_x, best.tile_y, best.chunk,
                              best.steps_per_launch, best.block)
     sim2.close()
+
+
+def test_autotune_cache_file(tmp_path, monkeypatch):
+    import torch
+
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("KGS_TUNE_CACHE", str(path))
+    arch = torch.cuda.get_device_properties(0).gcnArchName.replace(" ", "_")
+    # a hand-written line for a grid no other test tunes (sweeps of 128
+    # threads): reused as it stands, without timing
+    path.write_text(f"not a tuning line\nkgs-tune-v1 {arch} 3 42 0 {kgs.KGS_KERNEL_SWEEP} "
+                    "128 0 0 0 0\n")
+    p = workloads.random_problem(3, 42, seed=9, tau=0.03, amp=0.5)
+    say("autotune cache file")
+    sim = kgs.simulation_from_problem(p)
+    got = sim.autotune(steps=1, use_cache=True)
+    assert (got.kernel, got.block) == (kgs.KGS_KERNEL_SWEEP, 128)
+    assert (sim.tuning.kernel, sim.tuning.block) == (kgs.KGS_KERNEL_SWEEP, 128)
+    sim.step(2)
+    a = sim.read_state()
+    sim.close()
+    (b, _) = run(p, 2)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    # a winner found by timing is appended to the file
+    q = workloads.random_problem(3, 44, seed=10, tau=0.03, amp=0.5)
+    sim = kgs.simulation_from_problem(q)
+    best = sim.autotune(steps=1, use_cache=False)
+    sim.close()
+    last = path.read_text().strip().splitlines()[-1].split()
+    assert last[:5] == ["kgs-tune-v1", arch, "3", "44", "0"]
+    assert [int(v) for v in last[5:]] == [best.kernel, best.block, best.tile_x, best.tile_y,
+                                          best.chunk, best.steps_per_launch]
