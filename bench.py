@@ -33,7 +33,7 @@ METRIC = "lattice-point updates/s + % HBM roofline (3D 256³ FP64); served p50/p
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["3d", "batched", "serving", "1d", "2d", "paper2d",
+    ap.add_argument("--workload", choices=["3d", "batched", "batched3d", "serving", "1d", "2d", "paper2d",
                                            "paper3d"], default="3d",
                     help="3d: the headline line (default); batched: 64 uneven 2-D instances; "
                          "serving: Poisson request stream; 1d/2d: the 1-D and 2-D configurations; "
@@ -226,28 +226,39 @@ def _timed_ms(torch, stream, fn):
 
 def bench_batched(args):
     """64 uneven 2-D instances (n uniform in {128, 192, ..., 1024}), 500 steps
-    each: one launch sequence per instance vs batched launches vs batched
-    launches replayed from a hipGraph; all three end bitwise equal.  Each
-    mode is timed on its second run from the initial state."""
+    each, or (--workload batched3d) 16 uneven 3-D instances (n uniform in
+    {64, 96, ..., 256}), 40 steps each: one launch sequence per instance vs
+    batched launches vs batched launches replayed from a hipGraph; all three
+    end bitwise equal.  Each mode is timed on its second run from the
+    initial state."""
     import numpy as np
     import torch
 
     from paper_2502_09537_amd import kgs, workloads
 
     prec = workloads.FP32 if args.precision == "fp32" else workloads.FP64
-    steps = args.steps or 500
-    probs = workloads.batched_instances(count=64, steps=steps, precision=prec)
+    three = args.workload == "batched3d"
+    steps = args.steps or (40 if three else 500)
+    if three:
+        probs = workloads.batched3d_instances(count=16, steps=steps, precision=prec)
+    else:
+        probs = workloads.batched_instances(count=64, steps=steps, precision=prec)
+    pick = (0, 7, 15) if three else (0, 17, 63)
     points = sum(p.points for p in probs)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     results = {}
     finals = {}
-    for mode in ("per_instance", "batched", "batched_graph"):
+    for mode in ("per_instance", "batched", "batched_graph", "batched_tuned"):
         sims = [kgs.simulation_from_problem(p) for p in probs]
         if mode == "per_instance":
             run = lambda: [s.step(steps) for s in sims]
         else:
-            b = kgs.Batch(sims, graph=(mode == "batched_graph"))
+            b = kgs.Batch(sims, graph=(mode != "batched"))
+            if mode == "batched_tuned":
+                # untimed: the batch tuner times each group's launch
+                # configurations on the initial states (left unchanged)
+                b.autotune(steps=4, use_cache=False)
             run = lambda: b.step(steps)
         # every mode: one untimed run (first launches, the GPU's clock ramp,
         # and in graph mode the capture), then the timed run from the
@@ -258,29 +269,32 @@ def bench_batched(args):
             s.write_state(p.psi, p.u, p.v)
         ms, wall = _timed_ms(torch, stream, run)
         results[mode] = {"ms": ms, "updates_per_s": points * steps / (wall / 1e3)}
-        finals[mode] = [sims[i].read_state() for i in (0, 17, 63)]
+        finals[mode] = [sims[i].read_state() for i in pick]
         if mode != "per_instance":
             b.close()
         for s in sims:
             s.close()
-    identical = all(np.array_equal(x, y) for m in ("batched", "batched_graph")
+    identical = all(np.array_equal(x, y) for m in ("batched", "batched_graph", "batched_tuned")
                     for a, b2 in zip(finals["per_instance"], finals[m]) for x, y in zip(a, b2))
     best = max(results, key=lambda m: results[m]["updates_per_s"])
-    out = {"metric": "lattice-point updates/s (batched 2-D instances)",
+    what = ("16 3-D instances n in {64..256 step 32}, box [-8,8)^3, tau=0.002" if three else
+            "64 2-D instances n in {128..1024 step 64}")
+    out = {"metric": f"lattice-point updates/s (batched {'3-D' if three else '2-D'} instances)",
            "value": results[best]["updates_per_s"], "unit": "lattice-point updates/s",
            "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": results[best]["ms"] / steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"batched: 64 2-D instances n in {{128..1024 step 64}}, "
-                                  f"params U[0.5,2], {steps} steps, {args.precision}",
+           "config": {"workload": f"batched: {what}, params U[0.5,2], {steps} steps, "
+                                  f"{args.precision}",
                       "points": points, "state": args.precision, "best_mode": best},
            "modes": results, "bitwise_identical_across_modes": identical,
            "speedup_vs_per_instance": results[best]["updates_per_s"] /
            results["per_instance"]["updates_per_s"]}
     if prec == workloads.FP32:
-        sample = [probs[i] for i in (0, 17, 63)]
+        sample = [probs[i] for i in pick]
         out["fp32_max_rel_err_vs_fp64"] = fp32_vs_fp64(kgs, sample, finals["batched"], steps)
-        out["fp32_error_sample"] = "instances 0, 17, 63 after the run, against float64 runs"
+        out["fp32_error_sample"] = (f"instances {', '.join(map(str, pick))} after the run, "
+                                    "against float64 runs")
     print(json.dumps(out), flush=True)
 
 
@@ -562,7 +576,7 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "the library runs one simulation on one GPU; --gpus must be 1"}))
         sys.exit(2)
-    if args.workload == "batched":
+    if args.workload in ("batched", "batched3d"):
         return bench_batched(args)
     if args.workload == "serving":
         return bench_serving(args)

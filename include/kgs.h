@@ -284,6 +284,21 @@ int kgs_batch_set_graph(kgs_batch *b, int32_t enable);
  * failed wait or release (every release is attempted). */
 int kgs_batch_free(kgs_batch *b);
 
+/* Time the launch configurations of each streaming group of the batch (the
+ * 2-D members: y-streaming chunks of 8..64 rows and tiles of 8x8 .. 32x32
+ * points of one colour; the 3-D members: plane chunks of 8..128) over
+ * uniform runs of `steps` steps (>= 2; a warm-up, then the faster of two
+ * timed runs, each from the members' states, which are restored), and keep
+ * the fastest for each group.  Every configuration gives bitwise the same
+ * states.  With use_cache != 0 a winner found earlier for a group of the
+ * same GPU architecture, dimension, precision and member sizes is reused
+ * without timing: found in this process, or read from the file that
+ * KGS_TUNE_CACHE names (see kgs_autotune; group lines carry the tag
+ * "kgs-group-v1").  Graphs captured before are discarded.  Needs one copy of
+ * a group's states in device memory while it runs; synchronises the batch's
+ * stream. */
+int kgs_batch_autotune(kgs_batch *b, int32_t steps, int32_t use_cache);
+
 /* Message of the last failure of b (or of kgs_batch_create for NULL). */
 const char *kgs_batch_last_error(const kgs_batch *b);
 

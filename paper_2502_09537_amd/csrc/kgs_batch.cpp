@@ -117,6 +117,72 @@ hipError_t destroy(kgs_batch *b)
     return err.e;
 }
 
+// The launch configuration of a streaming class.
+kgs::GroupTuning group_of(const BatchClass &c)
+{
+    kgs::GroupTuning t;
+    t.mode = c.s3 ? kgs::GROUP_STREAM3D : c.s2_tile ? kgs::GROUP_TILE2D : kgs::GROUP_STREAM2D;
+    t.chunk = c.s2_chunk;
+    t.ty = c.s2_ty;
+    t.tx = c.s2_tx;
+    return t;
+}
+
+// Gives a streaming class the configuration t if it fits every member
+// (else leaves the class as it is and returns false): the class fields and
+// the host copy of its member descriptors, apart from the state buffers and
+// the first-launch flags that refresh_descriptors writes.
+bool apply_group(kgs_batch *b, BatchClass &c, const kgs::GroupTuning &t)
+{
+    const size_t nm = c.members.size();
+    const int eb = c.precision == KGS_FP64 ? 8 : 4;
+    if ((t.mode == kgs::GROUP_STREAM3D) != (c.dim == 3) || t.chunk < 1) return false;
+    int64_t tb = 0;
+    for (size_t i = 0; i < nm; ++i) {
+        const kgs_sim *x = b->sims[c.members[i]];
+        const int n = x->geo.n;
+        if (t.mode == kgs::GROUP_STREAM3D) {
+            if (n < kStream3dMinN || !kgs::stream3d_list_ok(x->geo, t.chunk, eb)) return false;
+            tb += kgs::stream3d_member_items(n, t.chunk);
+        } else if (t.mode == kgs::GROUP_TILE2D) {
+            if (!kgs::tile2d_shape_ok(x->geo, t.ty, t.tx, 4, eb)) return false;
+            tb += kgs::tile2d_member_tiles(n, t.ty, t.tx);
+        } else {
+            if (kgs::stream2d_tasks(n, t.chunk) < 1) return false;
+            tb += kgs::stream2d_tasks(n, t.chunk);
+        }
+    }
+    if (tb > 0x7fffffff) return false;
+    c.s3 = t.mode == kgs::GROUP_STREAM3D;
+    c.s2 = !c.s3;
+    c.s2_tile = t.mode == kgs::GROUP_TILE2D;
+    c.s2_chunk = t.chunk;
+    c.s2_ty = t.ty;
+    c.s2_tx = t.tx;
+    tb = 0;
+    for (size_t i = 0; i < nm; ++i) {
+        const kgs_sim *x = b->sims[c.members[i]];
+        const int n = x->geo.n;
+        for (int v = 0; v < 3; ++v) {
+            kgs::Stream2dMember &m = c.h_s2[v * nm + i];
+            std::memset(&m, 0, sizeof(m));
+            m.stride = x->geo.stride;
+            m.task_begin = tb;
+            m.k = x->coef;
+            m.n = n;
+            m.chunk = c.s2_tile ? c.s2_ty : c.s2_chunk;
+            m.tiles_x = c.s3 ? 0 : c.s2_tile ? kgs::tile2d_tiles_x(n, c.s2_tx)
+                                             : kgs::stream2d_tiles_x(n);
+            // in/out/first are set by refresh_descriptors
+        }
+        tb += c.s3 ? kgs::stream3d_member_items(n, c.s2_chunk)
+                   : c.s2_tile ? kgs::tile2d_member_tiles(n, c.s2_ty, c.s2_tx)
+                               : kgs::stream2d_tasks(n, c.s2_chunk);
+    }
+    c.s2_tasks = tb;
+    return true;
+}
+
 // Copy every member's current state buffer (the 3-D streaming kernel swaps
 // buffers) into the device descriptors when one has changed.  The pinned
 // staging may still be read by an earlier queued copy, so wait for the batch
@@ -168,6 +234,37 @@ int refresh_descriptors(kgs_batch *b)
     return KGS_OK;
 }
 
+// A uniform run of nsteps >= 2 steps of a streaming class: launches of 2
+// steps, and of 1 step where needed to keep the number of launches even (so
+// that every member ends in its own buffer), then the closing red sweep.
+hipError_t enqueue_stream_class(kgs_batch *b, const BatchClass &c, int64_t nsteps)
+{
+    // K = 2a + r steps: a launches of 4 sweeps and r of 2, one 4 split into
+    // two 2s when that count is odd
+    const int64_t a = nsteps / 2, r = nsteps % 2;
+    const int64_t split = (a + r) % 2;
+    std::vector<int> stages(static_cast<size_t>(a - split), 4);
+    for (int64_t i = 0; i < 2 * split + r; ++i) stages.push_back(2);
+    const int nm = static_cast<int>(c.members.size());
+    kgs::Stream2dMember none;
+    std::memset(&none, 0, sizeof(none));
+    for (size_t i = 0; i < stages.size(); ++i) {
+        const kgs::Stream2dMember *list = c.d_s2 + (i == 0 ? 0 : (i % 2 ? 2 * nm : nm));
+        hipError_t e;
+        if (c.s3)
+            e = kgs::launch_stream3d_list(c.precision, stages[i], list, nm, c.s2_tasks, i == 0,
+                                          b->own);
+        else if (c.s2_tile)
+            e = kgs::launch_tile2d_list(c.precision, stages[i], c.s2_ty, c.s2_tx, none, list, nm,
+                                        c.s2_tasks, b->own, i == 0 ? 1 : 0);
+        else
+            e = kgs::launch_stream2d(c.precision, stages[i], none, list, nm, c.s2_tasks, b->own);
+        if (e != hipSuccess) return e;
+    }
+    return kgs::launch_batch_sweep(c.dim, c.precision, c.d_members, nm, c.blocks, nullptr, 0,
+                                   kgs::PASS_R_ADJ, b->own);
+}
+
 // Launch sequence of a uniform K-step run: one resident launch per resident
 // class, then R_BASE, (B_FULL, R_ADJ_BASE)^(K-1), B_FULL, R_ADJ, each as one
 // batched launch per sweep class.
@@ -182,37 +279,11 @@ hipError_t enqueue_uniform(kgs_batch *b, int64_t nsteps)
                                             b->own);
         if (e != hipSuccess) return e;
     }
-    // 2-D and 3-D streaming classes: launches of 2 steps, and of 1 step
-    // where needed to keep the number of launches even, then the closing red
-    // sweep
+    // 2-D and 3-D streaming classes
     const bool streamed = nsteps >= 2;
     for (auto &c : b->classes) {
         if (!(c.s2 || c.s3) || !streamed) continue;
-        // K = 2a + r steps: a launches of 4 sweeps and r of 2, one 4 split
-        // into two 2s when that count is odd
-        const int64_t a = nsteps / 2, r = nsteps % 2;
-        const int64_t split = (a + r) % 2;
-        std::vector<int> stages(static_cast<size_t>(a - split), 4);
-        for (int64_t i = 0; i < 2 * split + r; ++i) stages.push_back(2);
-        const int nm = static_cast<int>(c.members.size());
-        kgs::Stream2dMember none;
-        std::memset(&none, 0, sizeof(none));
-        for (size_t i = 0; i < stages.size(); ++i) {
-            const kgs::Stream2dMember *list = c.d_s2 + (i == 0 ? 0 : (i % 2 ? 2 * nm : nm));
-            hipError_t e;
-            if (c.s3)
-                e = kgs::launch_stream3d_list(c.precision, stages[i], list, nm, c.s2_tasks, i == 0,
-                                              b->own);
-            else if (c.s2_tile)
-                e = kgs::launch_tile2d_list(c.precision, stages[i], c.s2_ty, c.s2_tx, none, list,
-                                            nm, c.s2_tasks, b->own, i == 0 ? 1 : 0);
-            else
-                e = kgs::launch_stream2d(c.precision, stages[i], none, list, nm, c.s2_tasks,
-                                         b->own);
-            if (e != hipSuccess) return e;
-        }
-        hipError_t e = kgs::launch_batch_sweep(c.dim, c.precision, c.d_members, nm, c.blocks,
-                                               nullptr, 0, kgs::PASS_R_ADJ, b->own);
+        hipError_t e = enqueue_stream_class(b, c, nsteps);
         if (e != hipSuccess) return e;
     }
     auto sweep = [&](int kind) {
@@ -422,25 +493,10 @@ int kgs_batch_create(kgs_sim *const *sims, int32_t count, void *stream, kgs_batc
                     code = bhip(b, e, "descriptor allocation (2-D streaming)");
                     break;
                 }
-                int64_t tb = 0;
-                for (size_t i = 0; i < nm; ++i) {
-                    const kgs_sim *x = b->sims[c.members[i]];
-                    for (int v = 0; v < 3; ++v) {
-                        kgs::Stream2dMember &m = c.h_s2[v * nm + i];
-                        std::memset(&m, 0, sizeof(m));
-                        m.stride = x->geo.stride;
-                        m.task_begin = tb;
-                        m.k = x->coef;
-                        m.n = x->geo.n;
-                        m.chunk = c.s2_tile ? c.s2_ty : chunk;
-                        m.tiles_x = c.s2_tile ? kgs::tile2d_tiles_x(x->geo.n, c.s2_tx)
-                                              : kgs::stream2d_tiles_x(x->geo.n);
-                        // in/out/first are set by refresh_descriptors
-                    }
-                    tb += c.s2_tile ? kgs::tile2d_member_tiles(x->geo.n, c.s2_ty, c.s2_tx)
-                                    : kgs::stream2d_tasks(x->geo.n, chunk);
+                if (!apply_group(b, c, group_of(c))) {
+                    code = bfail(b, KGS_EINVAL, "2-D group does not fit its launch");
+                    break;
                 }
-                c.s2_tasks = tb;
             } else if (c.dim == 3) {
                 // 3-D runs of several steps: the z-streaming kernel over all
                 // members in one launch when every member is large enough
@@ -477,22 +533,10 @@ int kgs_batch_create(kgs_sim *const *sims, int32_t count, void *stream, kgs_batc
                     code = bhip(b, e, "descriptor allocation (3-D streaming)");
                     break;
                 }
-                int64_t tb = 0;
-                for (size_t i = 0; i < nm; ++i) {
-                    const kgs_sim *x = b->sims[c.members[i]];
-                    for (int v = 0; v < 3; ++v) {
-                        kgs::Stream2dMember &m = c.h_s2[v * nm + i];
-                        std::memset(&m, 0, sizeof(m));
-                        m.stride = x->geo.stride;
-                        m.task_begin = tb;
-                        m.k = x->coef;
-                        m.n = x->geo.n;
-                        m.chunk = chunk;
-                        // in/out/first are set by refresh_descriptors
-                    }
-                    tb += kgs::stream3d_member_items(x->geo.n, chunk);
+                if (!apply_group(b, c, group_of(c))) {
+                    code = bfail(b, KGS_EINVAL, "3-D group does not fit its launch");
+                    break;
                 }
-                c.s2_tasks = tb;
             }
         }
         if (code == KGS_OK && step_slots > 0) {
@@ -670,6 +714,113 @@ int kgs_batch_step_each(kgs_batch *b, const int64_t *nsteps)
         }
     }
     return end(b);
+}
+
+int kgs_batch_autotune(kgs_batch *b, int32_t steps, int32_t use_cache)
+{
+    KGS_TRACE("kgs_batch_autotune");
+    if (!b) return KGS_EINVAL;
+    if (steps < 2) return bfail(b, KGS_EINVAL, "steps must be >= 2 (streaming runs)");
+    int rc = begin(b);
+    if (rc != KGS_OK) return rc;
+    hipError_t e = hipSuccess;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    void *backup = nullptr;
+    bool retuned = false;
+    if ((e = hipEventCreate(&ea)) != hipSuccess || (e = hipEventCreate(&eb)) != hipSuccess)
+        rc = bhip(b, e, "hipEventCreate");
+    for (auto &c : b->classes) {
+        if (rc != KGS_OK) break;
+        if (!(c.s2 || c.s3)) continue;
+        std::vector<int> sizes;
+        for (int m : c.members) sizes.push_back(b->sims[m]->geo.n);
+        const std::string sig = kgs::group_signature(b->device, c.dim, c.precision, sizes);
+        kgs::GroupTuning cached;
+        if (use_cache && kgs::group_cache_get(sig, cached) && apply_group(b, c, cached)) {
+            retuned = true;
+            continue;
+        }
+        // the members' states, restored after every timed run
+        size_t total = 0;
+        for (int m : c.members) total += 8 * b->sims[m]->plane_bytes;
+        if ((e = hipMalloc(&backup, total)) != hipSuccess) {
+            rc = bhip(b, e, "hipMalloc (autotune state copy)");
+            break;
+        }
+        auto copy_states = [&](bool save) {
+            size_t off = 0;
+            for (int m : c.members) {
+                kgs_sim *x = b->sims[m];
+                const size_t bytes = 8 * x->plane_bytes;
+                char *bk = static_cast<char *>(backup) + off;
+                hipError_t r = hipMemcpyAsync(save ? bk : x->state, save ? x->state : bk, bytes,
+                                              hipMemcpyDeviceToDevice, b->own);
+                if (r != hipSuccess) return r;
+                off += bytes;
+            }
+            return hipSuccess;
+        };
+        e = copy_states(true);
+        std::vector<kgs::GroupTuning> cands{group_of(c)};  // the default first
+        if (c.dim == 3) {
+            for (int ch : {8, 16, 32, 64, 128}) cands.push_back({kgs::GROUP_STREAM3D, ch, 0, 0});
+        } else {
+            for (int ch : {8, 16, 32, 64}) cands.push_back({kgs::GROUP_STREAM2D, ch, 0, 0});
+            const int tiles[][2] = {{8, 8}, {8, 16}, {16, 16}, {16, 32}, {32, 32}};
+            for (const auto &t : tiles) cands.push_back({kgs::GROUP_TILE2D, t[0], t[0], t[1]});
+        }
+        const kgs::GroupTuning original = group_of(c);
+        kgs::GroupTuning best = original;
+        float best_ms = -1.0f;
+        for (const kgs::GroupTuning &t : cands) {
+            if (e != hipSuccess) break;
+            if (!apply_group(b, c, t)) continue;
+            b->uploaded = false;
+            if ((rc = refresh_descriptors(b)) != KGS_OK) break;
+            // one warm-up run, then the faster of two timed runs, each from
+            // the saved states
+            float ms = -1.0f;
+            for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+                float m = 0.0f;
+                if ((e = hipEventRecord(ea, b->own)) != hipSuccess ||
+                    (e = enqueue_stream_class(b, c, steps)) != hipSuccess ||
+                    (e = hipEventRecord(eb, b->own)) != hipSuccess ||
+                    (e = hipEventSynchronize(eb)) != hipSuccess ||
+                    (e = hipEventElapsedTime(&m, ea, eb)) != hipSuccess ||
+                    (e = copy_states(false)) != hipSuccess)
+                    break;
+                if (rep > 0 && (ms < 0.0f || m < ms)) ms = m;
+            }
+            if (e == hipSuccess && (best_ms < 0.0f || ms < best_ms)) {
+                best_ms = ms;
+                best = t;
+            }
+        }
+        const hipError_t s2 = hipStreamSynchronize(b->own);
+        if (e == hipSuccess) e = s2;
+        const hipError_t fr = hipFree(backup);
+        backup = nullptr;
+        if (e == hipSuccess) e = fr;
+        if (e != hipSuccess && rc == KGS_OK) rc = bhip(b, e, "autotune run");
+        apply_group(b, c, rc == KGS_OK ? best : original);
+        if (rc == KGS_OK) kgs::group_cache_put(sig, best);
+        retuned = true;
+    }
+    kgs::FirstError err;
+    if (ea) err(hipEventDestroy(ea));
+    if (eb) err(hipEventDestroy(eb));
+    if (backup) err(hipFree(backup));
+    if (retuned) {
+        // captured runs embed the old launches
+        for (auto &kv : b->graphs) err(hipGraphExecDestroy(kv.second));
+        b->graphs.clear();
+        b->uploaded = false;
+        const int r2 = refresh_descriptors(b);
+        if (rc == KGS_OK) rc = r2;
+    }
+    if (!err.ok() && rc == KGS_OK) rc = bhip(b, err.e, "autotune release");
+    const int r3 = end(b);
+    return rc == KGS_OK ? r3 : rc;
 }
 
 int kgs_batch_free(kgs_batch *b)

@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include <hip/hip_runtime_api.h>
 
@@ -60,6 +61,21 @@ int default_kernel(const kgs_config &cfg);
 kgs_tuning default_tuning_of(const kgs_config &cfg);
 // Give the handle its second state buffer (ping-pong kernels) if it has none.
 int sim_ensure_state2(kgs_sim *s);
+// Launch configuration of a streaming group in a batch: mode GROUP_STREAM2D
+// (y-streaming, rows per task `chunk`), GROUP_TILE2D (tiles of ty rows x
+// tx compressed positions) or GROUP_STREAM3D (z-streaming over a member
+// list, planes per workgroup `chunk`).
+enum { GROUP_STREAM2D = 0, GROUP_TILE2D = 1, GROUP_STREAM3D = 2 };
+struct GroupTuning {
+    int mode = GROUP_STREAM2D, chunk = 0, ty = 0, tx = 0;
+};
+// Tuned group configurations (kgs_tune.cpp): the signature of a group
+// (architecture of the device, dimension, precision, sorted member sizes),
+// and a cache of winners in this process and, when KGS_TUNE_CACHE names a
+// file, in that file.
+std::string group_signature(int device, int dim, int precision, std::vector<int> sizes);
+bool group_cache_get(const std::string &sig, GroupTuning &t);
+void group_cache_put(const std::string &sig, const GroupTuning &t);
 // Bytes of one state buffer (8 planes) of a valid cfg.
 int64_t state_bytes(const kgs_config &cfg);
 // Sets the calling thread's last error (kgs_last_error(NULL)); returns code.

@@ -8,6 +8,7 @@
 // any process (the last line for a key wins).
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -149,7 +150,68 @@ std::vector<kgs_tuning> candidates(const kgs_sim *s)
     return out;
 }
 
+// Winners of batch groups (kgs_batch_autotune), keyed by group signature.
+std::map<std::string, kgs::GroupTuning> g_groups;
+std::string g_groups_loaded;  // the cache file whose group lines are in g_groups
+constexpr const char *kGroupTag = "kgs-group-v1";
+
+// Group lines: tag, then the signature's words (architecture, dim,
+// precision, member sizes joined by commas), then mode chunk ty tx.
+void load_groups_locked(const std::string &path)
+{
+    if (path.empty() || path == g_groups_loaded) return;
+    g_groups_loaded = path;
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return;
+    char line[8192];
+    while (std::fgets(line, sizeof(line), f)) {
+        char tag[32], arch[256], sizes[7680];
+        int dim, prec;
+        kgs::GroupTuning t;
+        if (std::sscanf(line, "%31s %255s %d %d %7679s %d %d %d %d", tag, arch, &dim, &prec, sizes,
+                        &t.mode, &t.chunk, &t.ty, &t.tx) == 9 &&
+            std::strcmp(tag, kGroupTag) == 0)
+            g_groups[std::string(arch) + " " + std::to_string(dim) + " " + std::to_string(prec) +
+                     " " + sizes] = t;
+    }
+    std::fclose(f);
+}
+
 }  // namespace
+
+namespace kgs {
+
+std::string group_signature(int device, int dim, int precision, std::vector<int> sizes)
+{
+    std::sort(sizes.begin(), sizes.end());
+    std::string s = arch_of(device) + " " + std::to_string(dim) + " " + std::to_string(precision) + " ";
+    for (size_t i = 0; i < sizes.size(); ++i) s += (i ? "," : "") + std::to_string(sizes[i]);
+    return s;
+}
+
+bool group_cache_get(const std::string &sig, GroupTuning &t)
+{
+    std::lock_guard<std::mutex> lock(g_cache_mutex);
+    load_groups_locked(cache_file());
+    auto it = g_groups.find(sig);
+    if (it == g_groups.end()) return false;
+    t = it->second;
+    return true;
+}
+
+void group_cache_put(const std::string &sig, const GroupTuning &t)
+{
+    std::lock_guard<std::mutex> lock(g_cache_mutex);
+    g_groups[sig] = t;
+    const std::string path = cache_file();
+    if (path.empty()) return;
+    FILE *f = std::fopen(path.c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, "%s %s %d %d %d %d\n", kGroupTag, sig.c_str(), t.mode, t.chunk, t.ty, t.tx);
+    std::fclose(f);
+}
+
+}  // namespace kgs
 
 extern "C" int kgs_autotune(kgs_sim *s, int32_t steps, int32_t use_cache, kgs_tuning *best)
 {

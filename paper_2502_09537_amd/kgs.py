@@ -32,7 +32,7 @@ EXPORTS = (
     "kgs_batch_free", "kgs_batch_last_error",
     "kgs_server_create", "kgs_server_submit", "kgs_server_run", "kgs_server_poll",
     "kgs_server_result", "kgs_server_release", "kgs_server_cancel", "kgs_server_stats",
-    "kgs_server_free", "kgs_server_last_error", "kgs_step_fields",
+    "kgs_server_free", "kgs_server_last_error", "kgs_step_fields", "kgs_batch_autotune",
 )
 KGS_REQ_QUEUED, KGS_REQ_RUNNING, KGS_REQ_DONE, KGS_REQ_FAILED, KGS_REQ_CANCELLED = range(5)
 
@@ -124,6 +124,7 @@ def lib():
             "kgs_batch_step_each": ([_VP, P(ctypes.c_int64)], ctypes.c_int),
             "kgs_batch_set_graph": ([_VP, ctypes.c_int32], ctypes.c_int),
             "kgs_batch_free": ([_VP], ctypes.c_int),
+            "kgs_batch_autotune": ([_VP, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
             "kgs_batch_last_error": ([_VP], ctypes.c_char_p),
             "kgs_server_create": ([P(KgsServerConfig), _VP, P(_VP)], ctypes.c_int),
             "kgs_server_submit": ([_VP, P(KgsConfig), _VP, _VP, _VP, _VP, ctypes.c_int32,
@@ -414,6 +415,12 @@ class Batch:
             raise ValueError("one step count per simulation")
         arr = (ctypes.c_int64 * len(self.sims))(*[int(k) for k in nsteps])
         self._check(lib().kgs_batch_step_each(self.handle, arr))
+        return self
+
+    def autotune(self, steps: int = 4, use_cache: bool = True) -> "Batch":
+        """Pick the fastest launch configuration of each streaming group
+        (kgs_batch_autotune); the states are unchanged."""
+        self._check(lib().kgs_batch_autotune(self.handle, int(steps), int(bool(use_cache))))
         return self
 
     def close(self) -> None:

@@ -250,6 +250,24 @@ def batched_instances(count: int = 64, seed: int = 20250213, steps: int = 500,
     return out
 
 
+def batched3d_instances(count: int = 16, seed: int = 20250213, steps: int = 40,
+                        precision: int = FP64, sizes=None) -> List[Problem]:
+    """3-D batches: `count` instances on [-8,8)^3, tau = 0.002, n drawn
+    uniformly from {64, 96, ..., 256} (the 3-D sizes of the serving mix),
+    (kappa1, kappa2, mu, gamma) ~ U[0.5, 2], Gaussian psi0/u0 with seeded
+    centres in [-4, 4]^3."""
+    rng = np.random.default_rng(seed)
+    if sizes is None:
+        sizes = list(range(64, 257, 32))
+    out = []
+    for i in range(count):
+        n = int(rng.choice(sizes))
+        out.append(gaussian_problem(3, n, int(rng.integers(1 << 31)), -8.0, 8.0, 0.002, steps,
+                                    precision))
+        out[-1].name = f"batch3d{i}"
+    return out
+
+
 @dataclass
 class Request:
     """One serving request: a problem and its arrival time in seconds."""

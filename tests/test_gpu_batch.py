@@ -272,3 +272,53 @@ def test_batch_3d_streaming_equals_individual_runs_and_oracle(graph, calls):
             ref2.append(s.read_state())
             s.close()
         assert same(again, ref2)
+
+
+def tuner_problems(seed=0):
+    # a 2-D streaming group, a 3-D member-list group, a resident member and a
+    # 3-D member below the list kernel's size (its class sweeps)
+    specs = [(2, 96, 0), (2, 130, 0), (2, 200, 0), (3, 32, 0), (3, 40, 0), (3, 66, 0),
+             (2, 34, 0), (3, 20, 1), (2, 90, 1), (2, 160, 1)]
+    return [workloads.random_problem(d, n, seed=seed * 100 + i, tau=0.03, amp=0.5, precision=prec)
+            for i, (d, n, prec) in enumerate(specs)]
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_autotune_keeps_states_and_results(graph, tmp_path, monkeypatch):
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("KGS_TUNE_CACHE", str(path))
+    probs = tuner_problems(5 + int(graph))
+    say("batch autotune, graph =", graph)
+    sims = [kgs.simulation_from_problem(p) for p in probs]
+    b = kgs.Batch(sims, graph=graph)
+    b.step(3)  # captured first when graph=True
+    before = states(sims)
+    b.autotune(steps=2, use_cache=False)
+    assert same(states(sims), before)
+    b.step(3)  # recaptured with the tuned launches
+    b.step(3)
+    got = states(sims)
+    b.close()
+    for s in sims:
+        s.close()
+    ref = []
+    for p in probs:
+        s = kgs.simulation_from_problem(p)
+        s.step(9)
+        ref.append(s.read_state())
+        s.close()
+    assert same(got, ref)
+    match_oracle(probs, got, 9, f"tuned batch (graph={graph})")
+    lines = [l.split() for l in path.read_text().splitlines() if l.startswith("kgs-group-v1")]
+    assert sorted(int(l[2]) for l in lines) == [2, 2, 3]  # fp64 2-D, fp32 2-D, fp64 3-D groups
+    # a second batch of the same groups reuses the winners without timing
+    sims = [kgs.simulation_from_problem(p) for p in probs]
+    b = kgs.Batch(sims)
+    b.autotune(steps=2, use_cache=True)
+    b.step(9)
+    again = states(sims)
+    b.close()
+    for s in sims:
+        s.close()
+    assert same(again, ref)
+    assert len([l for l in path.read_text().splitlines() if l.startswith("kgs-group-v1")]) == 3
