@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--round-work", type=int, default=0,
                     help="serving: point-steps per big-grid round (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-served", action="store_true",
+                    help="3d: skip the served-latency run (p50/p99 of the serving mix)")
     ap.add_argument("--cpu-steps", type=int, default=4,
                     help="oracle steps on the full grid for the CPU baseline")
     return ap.parse_args()
@@ -298,7 +300,7 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_serving(args):
+def bench_serving(args, only=None, emit=True):
     """Poisson request stream (mean --rate per second; 1-D n in [256, 8192],
     2-D n in [128, 1024], 3-D n in [64, 256], steps in [100, 2000], fp32 or
     fp64 at random), replayed in real time against the continuous-batching
@@ -331,6 +333,8 @@ def bench_serving(args):
              "one_at_a_time": dict(max_active=1, steps_per_round=0),
              "saturated": dict(max_active=0, steps_per_round=args.round_steps,
                                round_work=args.round_work)}
+    if only:  # these modes, in this order
+        modes = {m: modes[m] for m in only}
     offered = work / (reqs[-1].arrival - reqs[0].arrival)
     check_ids = []
 
@@ -425,7 +429,9 @@ def bench_serving(args):
     out["value"] = best["solves_per_s"]
     out["ms_per_step"] = None
     out["p50_s"], out["p99_s"] = best["p50_s"], best["p99_s"]
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_small_dims(args):
@@ -733,6 +739,18 @@ def main():
         out["copy_calibration"] = {"bytes_read": a.numel() * 8, "bytes_written": a.numel() * 8,
                                    "ms": s0.elapsed_time(s1) / 10,
                                    "GBs": 2 * a.numel() * 8 / (s0.elapsed_time(s1) / 10 / 1e3) / 1e9}
+    if not args.no_served:
+        # the metric's served latencies: the continuous-batching server on the
+        # serving mix (Poisson arrivals, 1-/2-/3-D requests), replayed in real
+        # time, and the same requests submitted at once for the capacity and
+        # the offered load
+        sv = bench_serving(args, only=("continuous", "saturated"), emit=False)
+        out["served"] = {"workload": sv["config"]["workload"], "p50_s": sv["p50_s"],
+                         "p99_s": sv["p99_s"], "solves_per_s": sv["value"],
+                         "lattice_updates_per_s": sv["continuous"]["lattice_updates_per_s"],
+                         "capacity_updates_per_s": sv["saturated"]["capacity_updates_per_s"],
+                         "offered_load_rho": sv["offered_load_rho"],
+                         "mix_equals_alone_bitwise": sv["mix_equals_alone_bitwise"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(workloads.config_3d(n=args.n), args.cpu_steps)
     print(json.dumps(out), flush=True)

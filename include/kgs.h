@@ -310,11 +310,15 @@ const char *kgs_batch_last_error(const kgs_batch *b);
  * start together in one persistent resident launch per round and run all
  * their steps; all other grids advance in rounds of up to steps_per_round
  * steps, the requests with the least remaining work first, up to round_work
- * point-steps per round (3-D grids of n >= 96 with their own streaming
- * kernel, 2-D grids advanced together 2 steps per launch, the rest in one
+ * point-steps per round (3-D grids of n >= 96 together in launches of the
+ * z-streaming kernel over a member list, 2-D grids advanced together 2 steps
+ * per launch, the rest in one
  * batched launch sequence).  A request that arrives while
  * others run joins at the next round.  Finished requests are retired to host
- * memory and their device memory returns to the server's pool.  Host code
+ * memory and their device memory returns to the server's pool.  A freed
+ * server's streams are kept and given to the next server created on the
+ * same device (a server made with new streams after other device work can
+ * run markedly slower).  Host code
  * does not wait for the GPU between rounds, except to keep at most two
  * rounds queued ahead.  A request's result is bitwise the state that
  * kgs_step gives when the same simulation runs alone.
