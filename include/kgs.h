@@ -253,9 +253,11 @@ int64_t kgs_required_bytes(const kgs_config *cfg);
  * and precisions) advanced together, one launch per (dimension, precision)
  * class over all members instead of one launch per simulation: members that
  * fit one workgroup run a whole call in one persistent launch; 2-D members
- * run 2 steps per launch (y-streaming or tiled kernel) in uniform runs of 2
- * or more steps; every other run is one launch per colour sweep.  A uniform
- * run can be captured once in a hipGraph and replayed.
+ * run 2 steps per launch (y-streaming or tiled kernel) and 3-D members of
+ * n >= 32 run 2 steps per launch of the z-streaming kernel (16x16 tiles in
+ * float64, 16x32 in float32), in uniform runs of 2 or more steps; every
+ * other run is one launch per colour sweep.  A uniform run can be captured
+ * once in a hipGraph and replayed.
  * Every member ends bitwise where kgs_step would have left it (points of one
  * colour are independent, sec. 4.2, so the launch layout does not matter).
  * ---------------------------------------------------------------------- */

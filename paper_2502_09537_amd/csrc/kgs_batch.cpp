@@ -143,7 +143,7 @@ bool apply_group(kgs_batch *b, BatchClass &c, const kgs::GroupTuning &t)
         const int n = x->geo.n;
         if (t.mode == kgs::GROUP_STREAM3D) {
             if (n < kStream3dMinN || !kgs::stream3d_list_ok(x->geo, t.chunk, eb)) return false;
-            tb += kgs::stream3d_member_items(n, t.chunk);
+            tb += kgs::stream3d_member_items(n, t.chunk, eb);
         } else if (t.mode == kgs::GROUP_TILE2D) {
             if (!kgs::tile2d_shape_ok(x->geo, t.ty, t.tx, 4, eb)) return false;
             tb += kgs::tile2d_member_tiles(n, t.ty, t.tx);
@@ -175,7 +175,7 @@ bool apply_group(kgs_batch *b, BatchClass &c, const kgs::GroupTuning &t)
                                              : kgs::stream2d_tiles_x(n);
             // in/out/first are set by refresh_descriptors
         }
-        tb += c.s3 ? kgs::stream3d_member_items(n, c.s2_chunk)
+        tb += c.s3 ? kgs::stream3d_member_items(n, c.s2_chunk, c.precision == KGS_FP64 ? 8 : 4)
                    : c.s2_tile ? kgs::tile2d_member_tiles(n, c.s2_ty, c.s2_tx)
                                : kgs::stream2d_tasks(n, c.s2_chunk);
     }
@@ -507,7 +507,7 @@ int kgs_batch_create(kgs_sim *const *sims, int32_t count, void *stream, kgs_batc
                 auto items = [&](int ch) {
                     int64_t t = 0;
                     for (size_t i = 0; i < nm; ++i)
-                        t += kgs::stream3d_member_items(b->sims[c.members[i]]->geo.n, ch);
+                        t += kgs::stream3d_member_items(b->sims[c.members[i]]->geo.n, ch, eb);
                     return t;
                 };
                 int chunk = 128;
@@ -553,7 +553,7 @@ int kgs_batch_create(kgs_sim *const *sims, int32_t count, void *stream, kgs_batc
     }
     if (code != KGS_OK) {
         g_batch_err = b->err;
-        destroy(b);
+        (void)destroy(b);  // the first error is the one reported
         delete b;
         return code;
     }

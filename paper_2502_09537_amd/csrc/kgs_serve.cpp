@@ -762,15 +762,16 @@ int run_stream2d(kgs_server *s, int prec, int64_t k, const std::vector<Request *
 
 // 3-D requests of one precision taking k >= 2 steps this round: the same
 // launch sequence as run_stream2d with the z-streaming kernel's member-list
-// launch over all of them (16x16 tiles, the longest plane chunk that still
-// gives a workgroup per CU), then the closing red sweep as one batched
-// sweep.
+// launch over all of them (the list tile of the precision, the longest
+// plane chunk that still gives a workgroup per CU), then the closing red
+// sweep as one batched sweep.
 int run_stream3d(kgs_server *s, int prec, int64_t k, const std::vector<Request *> &rs)
 {
     const int nm = static_cast<int>(rs.size());
+    const int eb = prec == KGS_FP64 ? 8 : 4;
     auto items = [&](int ch) {
         int64_t t = 0;
-        for (const Request *r : rs) t += kgs::stream3d_member_items(r->sim->geo.n, ch);
+        for (const Request *r : rs) t += kgs::stream3d_member_items(r->sim->geo.n, ch, eb);
         return t;
     };
     int chunk = 128;
@@ -798,7 +799,7 @@ int run_stream3d(kgs_server *s, int prec, int64_t k, const std::vector<Request *
             m.chunk = chunk;
             m.first = v == 0 ? 1 : 0;
         }
-        tb += kgs::stream3d_member_items(x->geo.n, chunk);
+        tb += kgs::stream3d_member_items(x->geo.n, chunk, eb);
         std::memset(&bm[i], 0, sizeof(bm[i]));
         bm[i].state = x->state;
         bm[i].stride = x->geo.stride;

@@ -96,14 +96,16 @@ __host__ __device__ constexpr int lds_pitch(int bx) { return bx | 1; }
 // NL values of U.
 __host__ __device__ constexpr int lds_plane(int bx, int by) { return (lds_pitch(bx) * by + 1) & ~1; }
 
-// Largest workgroup per instantiation: the four-sweep pipeline keeps 16
-// planes of FIFO per thread and needs more than 128 VGPRs, so at most 3
-// waves per SIMD (12 per workgroup); a compiled-in tile has exactly its
-// block of threads.
+// Largest workgroup per instantiation: the four-sweep float64 pipeline
+// keeps 16 planes of FIFO per thread (128 VGPRs) and needs more, so at most
+// 3 waves per SIMD (12 per workgroup); in float32 the same FIFO takes 64
+// VGPRs and the kernel fits 128, so 16 waves.  A compiled-in tile has
+// exactly its block of threads.
 template <typename T, int S, int TX = 0, int TY = 0>
 constexpr int max_threads()
 {
-    return TX ? ((TX + 2 * ((S + 1) / 2)) * (TY + 2 * S) + 63) / 64 * 64 : S == 4 ? 768 : 1024;
+    return TX ? ((TX + 2 * ((S + 1) / 2)) * (TY + 2 * S) + 63) / 64 * 64
+              : S == 4 && sizeof(T) == 8 ? 768 : 1024;
 }
 
 // Per-thread pipeline registers.  Plane FIFOs are rings indexed by the
@@ -397,11 +399,12 @@ stream3d_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t stride, i
 
 // Several grids in one launch: member m owns the items [list[m].task_begin,
 // list[m + 1].task_begin) of the launch, each grid with its own state
-// buffers, constants, size and chunk, all with the compiled-in TX x TY
-// tile.
+// buffers, constants, size and chunk, all with one tile: TX x TY compiled
+// in, or tile_x x tile_y when TX = TY = 0.
 template <typename T, int S, bool FIRST, int TX, int TY>
 __global__ void __launch_bounds__((max_threads<T, S, TX, TY>()))
-stream3d_list_kernel(const Stream2dMember *__restrict__ list, int nm)
+stream3d_list_kernel(const Stream2dMember *__restrict__ list, int nm, int tile_x_arg,
+                     int tile_y_arg)
 {
     const int item = xcd_item();
     int lo = 0, hi = nm - 1;  // last member whose first item is <= item
@@ -413,9 +416,10 @@ stream3d_list_kernel(const Stream2dMember *__restrict__ list, int nm)
     const Stream2dMember &m = list[lo];
     const int n = m.n;
     const Coef k = m.k;
-    const int tiles_x = ((n >> 1) + TX - 1) / TX, tiles_y = (n + TY - 1) / TY;
+    const int tile_x = TX ? TX : tile_x_arg, tile_y = TY ? TY : tile_y_arg;
+    const int tiles_x = ((n >> 1) + tile_x - 1) / tile_x, tiles_y = (n + tile_y - 1) / tile_y;
     stream3d_item<T, S, FIRST, TX, TY>(static_cast<const T *>(m.in), static_cast<T *>(m.out),
-                                       m.stride, n, tiles_x, tiles_y, TX, TY, m.chunk,
+                                       m.stride, n, tiles_x, tiles_y, tile_x, tile_y, m.chunk,
                                        item - static_cast<int>(m.task_begin), k);
 }
 
@@ -437,8 +441,10 @@ hipError_t launch_typed(const Geometry &g, const StreamShape &sh, const T *in, T
     if (threads > max_threads<T, S>() || items > 0x7fffffff || lds > 160 * 1024)
         return hipErrorInvalidValue;
     // four-sweep launches of the 16x16 tile are compiled with the tile fixed
-    // (measured on MI355X: 16x16 beats taller tiles of up to 768 threads,
-    // e.g. 16x28, at 256^3 float64)
+    // (measured on MI355X at 256^3 float64: 16x16 beats taller tiles of up
+    // to 768 threads, e.g. 16x28).  Other shapes, among them the float32
+    // default 16x32, take it at run time: compiled in, 16x32 spills
+    // registers at the 128 VGPRs its 13 waves allow and lost 15%.
     auto kern = first ? stream3d_kernel<T, S, true, 0, 0> : stream3d_kernel<T, S, false, 0, 0>;
     if constexpr (S == 4) {
         if (sh.tile_x == 16 && sh.tile_y == 16)
@@ -451,38 +457,59 @@ hipError_t launch_typed(const Geometry &g, const StreamShape &sh, const T *in, T
     return hipGetLastError();
 }
 
-// Launches over member lists use the 16x16 tile, compiled in.
-constexpr int kListTile = 16;
+// Tile of the launches over member lists (compressed positions x rows),
+// the same for both sweep counts so that a member owns the same items in
+// every launch of a sequence.  float64: 16x16, compiled in (8 waves, the
+// LDS and registers of a workgroup per CU).  float32: 16x32 at run time
+// (13 waves at 128 VGPRs, half the LDS bytes): the halo rings add 0.64 of
+// the tile's columns instead of 0.88, and each SIMD holds 3-4 waves
+// (measured on MI355X at 256^3: 213 against 249 us per 2-step launch).
+struct ListTile {
+    int x, y;
+};
+
+ListTile list_tile(int elem_bytes) { return elem_bytes == 8 ? ListTile{16, 16} : ListTile{16, 32}; }
 
 template <typename T, int S>
 hipError_t launch_list_typed(const Stream2dMember *list, int nm, int64_t items, bool first,
                              hipStream_t s)
 {
-    constexpr int TX = kListTile, TY = kListTile;
-    constexpr int BX = TX + 2 * ((S + 1) / 2), BY = TY + 2 * S;
-    constexpr int threads = (BX * BY + 63) / 64 * 64;
+    const ListTile tl = list_tile(sizeof(T));
+    const int BX = tl.x + 2 * ((S + 1) / 2), BY = tl.y + 2 * S;
+    const int threads = (BX * BY + 63) / 64 * 64;
     const size_t lds = static_cast<size_t>(2) * S * 3 * lds_plane(BX, BY) * sizeof(T);
+    constexpr bool fixed = sizeof(T) == 8;
+    constexpr int TX = fixed ? 16 : 0, TY = fixed ? 16 : 0;
+    if (threads > max_threads<T, S, TX, TY>() || lds > 160 * 1024) return hipErrorInvalidValue;
     auto kern = first ? stream3d_list_kernel<T, S, true, TX, TY>
                       : stream3d_list_kernel<T, S, false, TX, TY>;
     hipError_t e = allow_dynamic_lds(reinterpret_cast<const void *>(kern), static_cast<int>(lds));
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(items)), dim3(threads), lds, s, list, nm);
+    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(items)), dim3(threads), lds, s, list, nm,
+                       tl.x, tl.y);
     return hipGetLastError();
 }
 
 }  // namespace
 
-int stream3d_list_tile() { return kListTile; }
-
-int64_t stream3d_member_items(int n, int chunk)
+void stream3d_list_tile(int elem_bytes, int *tile_x, int *tile_y)
 {
-    const int64_t tx = (n / 2 + kListTile - 1) / kListTile, ty = (n + kListTile - 1) / kListTile;
+    const ListTile tl = list_tile(elem_bytes);
+    *tile_x = tl.x;
+    *tile_y = tl.y;
+}
+
+int64_t stream3d_member_items(int n, int chunk, int elem_bytes)
+{
+    const ListTile tl = list_tile(elem_bytes);
+    const int64_t tx = (n / 2 + tl.x - 1) / tl.x, ty = (n + tl.y - 1) / tl.y;
     return tx * ty * ((n + chunk - 1) / chunk);
 }
 
 bool stream3d_list_ok(const Geometry &g, int chunk, int elem_bytes)
 {
-    const StreamShape sh = {kListTile, kListTile, chunk, 2};
+    const ListTile tl = list_tile(elem_bytes);
+    const StreamShape sh = {tl.x, tl.y, chunk, 2};
     return stream3d_shape_ok(g, sh, elem_bytes);
 }
 
@@ -511,7 +538,8 @@ bool stream3d_shape_ok(const Geometry &g, const StreamShape &sh, int elem_bytes)
     const int S = 2 * sh.steps;
     const int BX = sh.tile_x + 2 * ((S + 1) / 2), BY = sh.tile_y + 2 * S;
     const int NT = BX * BY;
-    const int limit = S == 4 ? max_threads<float, 4>() : max_threads<float, 2>();
+    const int limit = elem_bytes == 8 ? (S == 4 ? max_threads<double, 4>() : max_threads<double, 2>())
+                                      : (S == 4 ? max_threads<float, 4>() : max_threads<float, 2>());
     if ((NT + 63) / 64 * 64 > limit) return false;
     return static_cast<size_t>(2) * S * 3 * lds_plane(BX, BY) * elem_bytes <= 160 * 1024;
 }

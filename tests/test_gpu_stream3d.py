@@ -71,6 +71,56 @@ def test_stream_equals_sweep_bitwise(n, steps, tx, ty, chunk, spl, prec):
     assert ea == eb
 
 
+# float32 shapes beyond 12 waves per workgroup: the four-sweep float32
+# pipeline fits 128 VGPRs, so up to 16 waves (float64 stops at 12)
+F32_SHAPES = [
+    (70, 3, 16, 32, 20, 2),   # the float32 default tile (832 threads), ragged tiles and chunks
+    (66, 3, 32, 16, 64, 2),   # 896 threads, chunk longer than the grid
+    (40, 5, 16, 40, 7, 2),    # 960 threads
+    (34, 4, 16, 32, 9, 1),    # the default tile with 2 sweeps per launch
+]
+
+
+@pytest.mark.parametrize("n,steps,tx,ty,chunk,spl", F32_SHAPES)
+def test_fp32_wide_workgroups_equal_sweep_bitwise(n, steps, tx, ty, chunk, spl):
+    p = workloads.random_problem(3, n, seed=41 + n, tau=0.04, amp=0.5, precision=workloads.FP32)
+    say("fp32 stream vs sweep", n, steps, tx, ty, chunk, spl)
+    (a, ea) = run(p, steps)
+    (b, eb) = run(p, steps, tuning(tx, ty, chunk, spl))
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    assert ea == eb
+
+
+def test_wide_workgroups_are_float32_only():
+    say("16x32 tile: float32 only")
+    for prec, ok in ((workloads.FP32, True), (workloads.FP64, False)):
+        p = workloads.random_problem(3, 64, seed=2, precision=prec)
+        sim = kgs.simulation_from_problem(p)
+        try:
+            if ok:
+                sim.tuning = tuning(16, 32, 32, 2)
+                assert (sim.tuning.tile_x, sim.tuning.tile_y) == (16, 32)
+            else:
+                with pytest.raises(kgs.KgsError):
+                    sim.tuning = tuning(16, 32, 32, 2)
+        finally:
+            sim.close()
+
+
+@pytest.mark.parametrize("n,tile", [(96, (16, 16)), (128, (16, 32)), (256, (16, 32))])
+def test_default_fp32_3d_tile(n, tile):
+    p = workloads.random_problem(3, n, seed=3, precision=workloads.FP32)
+    say("fp32 default tile", n)
+    sim = kgs.simulation_from_problem(p)
+    try:
+        t = sim.tuning
+        assert t.kernel == kgs.KGS_KERNEL_STREAM
+        assert (t.tile_x, t.tile_y) == tile
+    finally:
+        sim.close()
+
+
 def test_stream_matches_oracle_3d_config_reduced():
     p = workloads.config_3d(n=32, steps=200)
     say("stream vs oracle 32^3 x 200")
