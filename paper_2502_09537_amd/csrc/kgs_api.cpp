@@ -18,6 +18,7 @@
 
 #include "kgs_trace.h"
 #include "kgs_internal.h"
+#include "kgs_plan.h"
 #include "kgs_sim.h"
 
 
@@ -165,11 +166,12 @@ kgs::Geometry make_geometry(const kgs_config &c)
 //    launch, 16x16 tiles in float64 and, from n = 128, 16x32 tiles in
 //    float32 (13 waves per workgroup: 17-24% faster than 16x16 at
 //    n = 192..512, 3-6% at 128, 30% slower at 96 where 16x32 tiles leave
-//    most CUs idle), the chunk of z-planes the longest power of two
-//    (8..128) that still gives about 200 workgroups;
+//    most CUs idle), the chunk of z-planes (8..128) that stream3d_chunk
+//    estimates to end the launch first on this device (the CUs take one
+//    workgroup each, so the items should fill whole rounds of them);
 //  * one colour sweep per launch otherwise (3-D below n = 96, 1-D grids
 //    beyond the resident kernel).
-kgs_tuning default_tuning(const kgs_config &c)
+kgs_tuning default_tuning(const kgs_config &c, bool with_chunk = true)
 {
     kgs_tuning t;
     std::memset(&t, 0, sizeof(t));
@@ -217,9 +219,7 @@ kgs_tuning default_tuning(const kgs_config &c)
     } else if (c.dim == 3 && c.n >= 96) {
         t.kernel = KGS_KERNEL_STREAM;
         if (c.precision == KGS_FP32 && c.n >= 128) t.tile_y = 32;
-        const int64_t tiles = static_cast<int64_t>((c.n / 2 + t.tile_x - 1) / t.tile_x) *
-                              ((c.n + t.tile_y - 1) / t.tile_y);
-        while (t.chunk > 8 && tiles * ((c.n + t.chunk - 1) / t.chunk) < 200) t.chunk /= 2;
+        if (with_chunk) t.chunk = kgs::stream3d_chunk(&c.n, 1, t.tile_x, t.tile_y, kgs::device_cus());
     }
     return t;
 }
@@ -229,7 +229,7 @@ int64_t bytes_for(const kgs_config &c)
     const kgs::Geometry g = make_geometry(c);
     const int64_t state = 8 * g.stride * static_cast<int64_t>(elem_bytes(c.precision));
     const int64_t partials = (2 * kgs::energy_partial_slots() + 2) * 8;
-    const int dk = default_tuning(c).kernel;
+    const int dk = default_tuning(c, false).kernel;
     const bool pingpong = dk == KGS_KERNEL_STREAM || dk == KGS_KERNEL_TILE;
     return state * (pingpong ? 2 : 1) + partials;
 }
@@ -485,7 +485,7 @@ int sim_create_pooled(const kgs_config *cfg, const double *P, const double *Q, c
     return KGS_OK;
 }
 
-int default_kernel(const kgs_config &cfg) { return default_tuning(cfg).kernel; }
+int default_kernel(const kgs_config &cfg) { return default_tuning(cfg, false).kernel; }
 
 kgs_tuning default_tuning_of(const kgs_config &cfg) { return default_tuning(cfg); }
 

@@ -21,6 +21,7 @@
 #include "kgs.h"
 #include "kgs_trace.h"
 #include "kgs_internal.h"
+#include "kgs_plan.h"
 #include "kgs_sim.h"
 
 namespace {
@@ -89,9 +90,8 @@ thread_local std::string g_batch_err;
 
 // 3-D members stream together when every member has n >= kStream3dMinN
 // (at least one full tile along x); the plane chunk of such a launch is the
-// longest that still gives kStream3dGroupItems workgroups (one per CU).
+// one stream3d_list_chunk estimates to end it first.
 constexpr int kStream3dMinN = 32;
-constexpr int64_t kStream3dGroupItems = 256;
 
 // Releases everything the batch holds; the first runtime error, if any.
 hipError_t destroy(kgs_batch *b)
@@ -500,8 +500,8 @@ int kgs_batch_create(kgs_sim *const *sims, int32_t count, void *stream, kgs_batc
             } else if (c.dim == 3) {
                 // 3-D runs of several steps: the z-streaming kernel over all
                 // members in one launch when every member is large enough
-                // for its tile (else batched sweeps), with the longest
-                // plane chunk (8..128) that still gives a workgroup per CU
+                // for its tile (else batched sweeps), with the plane chunk
+                // (8..128) estimated to end the launch first
                 const size_t nm = c.members.size();
                 const int eb = c.precision == KGS_FP64 ? 8 : 4;
                 auto items = [&](int ch) {
@@ -510,8 +510,9 @@ int kgs_batch_create(kgs_sim *const *sims, int32_t count, void *stream, kgs_batc
                         t += kgs::stream3d_member_items(b->sims[c.members[i]]->geo.n, ch, eb);
                     return t;
                 };
-                int chunk = 128;
-                while (chunk > 8 && items(chunk) < kStream3dGroupItems) chunk /= 2;
+                std::vector<int> sizes(nm);
+                for (size_t i = 0; i < nm; ++i) sizes[i] = b->sims[c.members[i]]->geo.n;
+                const int chunk = kgs::stream3d_list_chunk(sizes.data(), static_cast<int>(nm), eb);
                 bool ok = items(chunk) <= 0x7fffffff;
                 for (size_t i = 0; i < nm && ok; ++i) {
                     const kgs_sim *x = b->sims[c.members[i]];

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include "kgs_internal.h"
+#include "kgs_plan.h"
 
 namespace kgs {
 
@@ -22,6 +23,23 @@ hipError_t allow_dynamic_lds(const void *kernel, int bytes)
     e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e == hipSuccess) allowed[{dev, kernel}] = bytes;
     return e;
+}
+
+int device_cus()
+{
+    constexpr int kMi355xCus = 256;
+    static std::mutex mu;
+    static std::map<int, int> cus;  // device -> compute units
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return kMi355xCus;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cus.find(dev);
+    if (it != cus.end()) return it->second;
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1)
+        c = kMi355xCus;
+    cus[dev] = c;
+    return c;
 }
 
 }  // namespace kgs

@@ -47,14 +47,12 @@
 #include "kgs.h"
 #include "kgs_trace.h"
 #include "kgs_internal.h"
+#include "kgs_plan.h"
 #include "kgs_sim.h"
 
 namespace {
 
 constexpr int64_t kDefaultRoundWork = int64_t(1) << 31;  // point-steps per big-lane round
-// plane chunk of a 3-D member-list launch: the longest (8..128) that still
-// gives this many workgroups (one per CU)
-constexpr int64_t kStream3dGroupItems = 256;
 constexpr size_t kMaxAhead = 2;                          // rounds queued ahead, per lane
 constexpr int kRingSlots = 16;                           // staging slots per lane
 constexpr int kSlotChunk = 1024;                         // energy slots per allocation
@@ -762,20 +760,16 @@ int run_stream2d(kgs_server *s, int prec, int64_t k, const std::vector<Request *
 
 // 3-D requests of one precision taking k >= 2 steps this round: the same
 // launch sequence as run_stream2d with the z-streaming kernel's member-list
-// launch over all of them (the list tile of the precision, the longest
-// plane chunk that still gives a workgroup per CU), then the closing red
-// sweep as one batched sweep.
+// launch over all of them (the list tile of the precision, the plane chunk
+// estimated to end the launch first), then the closing red sweep as one
+// batched sweep.
 int run_stream3d(kgs_server *s, int prec, int64_t k, const std::vector<Request *> &rs)
 {
     const int nm = static_cast<int>(rs.size());
     const int eb = prec == KGS_FP64 ? 8 : 4;
-    auto items = [&](int ch) {
-        int64_t t = 0;
-        for (const Request *r : rs) t += kgs::stream3d_member_items(r->sim->geo.n, ch, eb);
-        return t;
-    };
-    int chunk = 128;
-    while (chunk > 8 && items(chunk) < kStream3dGroupItems) chunk /= 2;
+    std::vector<int> sizes;
+    for (const Request *r : rs) sizes.push_back(r->sim->geo.n);
+    const int chunk = kgs::stream3d_list_chunk(sizes.data(), nm, eb);
     const size_t s3_bytes = align_up(3 * nm * sizeof(kgs::Stream2dMember), 256);
     const size_t bm_bytes = align_up(nm * sizeof(kgs::BatchMember), 256);
     int rc = KGS_OK;

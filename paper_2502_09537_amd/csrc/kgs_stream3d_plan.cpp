@@ -1,0 +1,91 @@
+// Launch planning for the z-streaming kernel (kgs_stream3d.hip): the plane
+// chunk whose launch is estimated to end first.
+#include <algorithm>
+#include <cstdint>
+#include <functional>
+#include <queue>
+#include <vector>
+
+#include "kgs_internal.h"
+#include "kgs_plan.h"
+
+namespace kgs {
+
+// A launch's workgroups are dealt to the 8 XCDs in turn, and xcd_item
+// gives XCD x the x-th eighth of the items in order (every item to XCD
+// item mod 8 when the count is not a multiple of 8); each XCD starts its
+// next item on the first of its CUs that is free.  An item of L planes
+// takes L + kItemSteps pipeline steps: on MI355X at 256^3 float64 a launch
+// of one round of 128-plane items took 260 us, of two rounds of 64-plane
+// items 291 us (145.5 per item), which puts the fixed cost of an item
+// (pipeline fill and drain, set-up) at 17 plane-steps.
+double stream3d_launch_steps(const int *n, int count, int tile_x, int tile_y, int chunk, int cus)
+{
+    constexpr int kItemSteps = 17;
+    constexpr int kXcds = 8;
+    constexpr int64_t kDealLimit = 16384;  // beyond: 64+ rounds, tail < 2%
+    if (count < 1 || cus < 1 || chunk < 1) return 0.0;
+    int64_t items = 0;
+    double work = 0.0;
+    int longest = 0;
+    for (int m = 0; m < count; ++m) {
+        const int64_t tiles =
+            static_cast<int64_t>((n[m] / 2 + tile_x - 1) / tile_x) * ((n[m] + tile_y - 1) / tile_y);
+        const int nc = (n[m] + chunk - 1) / chunk;
+        items += tiles * nc;
+        work += static_cast<double>(tiles) * (n[m] + static_cast<double>(nc) * kItemSteps);
+        longest = std::max(longest, std::min(chunk, n[m]) + kItemSteps);
+    }
+    if (items > kDealLimit) return work / cus + longest;
+    // item lengths in item order: per member its tiles first, then its chunks
+    std::vector<int> len;
+    len.reserve(static_cast<size_t>(items));
+    for (int m = 0; m < count; ++m) {
+        const int64_t tiles =
+            static_cast<int64_t>((n[m] / 2 + tile_x - 1) / tile_x) * ((n[m] + tile_y - 1) / tile_y);
+        for (int z0 = 0; z0 < n[m]; z0 += chunk)
+            len.insert(len.end(), static_cast<size_t>(tiles), std::min(chunk, n[m] - z0) + kItemSteps);
+    }
+    const int groups = cus % kXcds == 0 ? kXcds : 1;
+    const int per = cus / groups;
+    const bool slices = groups == kXcds && items % kXcds == 0;
+    double end = 0.0;
+    for (int x = 0; x < groups; ++x) {
+        std::priority_queue<int64_t, std::vector<int64_t>, std::greater<int64_t>> free_at;
+        for (int c = 0; c < per; ++c) free_at.push(0);
+        const int64_t first = groups == 1 ? 0 : slices ? x * (items / kXcds) : x;
+        const int64_t last = groups == 1 || !slices ? items : (x + 1) * (items / kXcds);
+        const int64_t step = groups == 1 || slices ? 1 : kXcds;
+        for (int64_t i = first; i < last; i += step) {
+            const int64_t t = free_at.top() + len[static_cast<size_t>(i)];
+            free_at.pop();
+            free_at.push(t);
+            end = std::max(end, static_cast<double>(t));
+        }
+    }
+    return end;
+}
+
+int stream3d_chunk(const int *n, int count, int tile_x, int tile_y, int cus)
+{
+    static const int kChunks[] = {128, 96, 64, 48, 32, 24, 16, 12, 8};
+    int best = kChunks[0];
+    double best_t = stream3d_launch_steps(n, count, tile_x, tile_y, best, cus);
+    for (int c : kChunks) {
+        const double t = stream3d_launch_steps(n, count, tile_x, tile_y, c, cus);
+        if (t < 0.99 * best_t) {
+            best = c;
+            best_t = t;
+        }
+    }
+    return best;
+}
+
+int stream3d_list_chunk(const int *n, int count, int elem_bytes)
+{
+    int tx = 0, ty = 0;
+    stream3d_list_tile(elem_bytes, &tx, &ty);
+    return stream3d_chunk(n, count, tx, ty, device_cus());
+}
+
+}  // namespace kgs

@@ -1,0 +1,33 @@
+// Prints the launch estimate and the chosen chunk of the z-streaming launch
+// planner for one group of grids: plan_driver tile_x tile_y cus chunk n...
+// (chunk 0: only the chosen chunk).  The planner's two device-facing
+// helpers are stood in for here: no GPU is needed.
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "kgs_plan.h"
+
+namespace kgs {
+void stream3d_list_tile(int elem_bytes, int *tile_x, int *tile_y)
+{
+    *tile_x = 16;
+    *tile_y = elem_bytes == 8 ? 16 : 32;
+}
+int device_cus() { return 256; }
+}  // namespace kgs
+
+int main(int argc, char **argv)
+{
+    if (argc < 6) return 2;
+    const int tx = std::atoi(argv[1]), ty = std::atoi(argv[2]), cus = std::atoi(argv[3]);
+    const int chunk = std::atoi(argv[4]);
+    std::vector<int> n;
+    for (int i = 5; i < argc; ++i) n.push_back(std::atoi(argv[i]));
+    const int count = static_cast<int>(n.size());
+    const int best = kgs::stream3d_chunk(n.data(), count, tx, ty, cus);
+    const double est = chunk > 0 ? kgs::stream3d_launch_steps(n.data(), count, tx, ty, chunk, cus) : 0.0;
+    std::printf("%d %.6f %d %d\n", best, est, kgs::stream3d_list_chunk(n.data(), count, 8),
+                kgs::stream3d_list_chunk(n.data(), count, 4));
+    return 0;
+}

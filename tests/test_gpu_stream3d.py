@@ -121,6 +121,26 @@ def test_default_fp32_3d_tile(n, tile):
         sim.close()
 
 
+@pytest.mark.parametrize("prec", [workloads.FP64, workloads.FP32])
+def test_default_chunk_on_a_grid_between_whole_rounds(prec):
+    # at 224^3 the items of 64-plane (float64) or 32-plane (float32) chunks
+    # fill 1.5 rounds of the CUs: the default takes longer chunks with a
+    # ragged last one (96, 96, 32 / 48 x 4, 32), bitwise the same state
+    p = workloads.random_problem(3, 224, seed=7, tau=0.02, amp=0.5, precision=prec)
+    say("default chunk 224^3", prec)
+    sim = kgs.simulation_from_problem(p)
+    try:
+        t = sim.tuning
+    finally:
+        sim.close()
+    assert t.kernel == kgs.KGS_KERNEL_STREAM and 8 <= t.chunk <= 128
+    (a, ea) = run(p, 2)
+    (b, eb) = run(p, 2, t)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    assert ea == eb
+
+
 def test_stream_matches_oracle_3d_config_reduced():
     p = workloads.config_3d(n=32, steps=200)
     say("stream vs oracle 32^3 x 200")

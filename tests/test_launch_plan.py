@@ -1,0 +1,112 @@
+"""CPU: the plane-chunk planner of the z-streaming launches
+(csrc/kgs_stream3d_plan.cpp).  A launch runs one workgroup per CU; its
+workgroups are dealt to the 8 XCDs in turn and each XCD starts its next work
+item (a tile of one grid by a chunk of its z-planes) on its first free CU,
+an item of L planes taking L + 17 plane-steps.  The planner's estimate is
+checked against closed forms (whole rounds) and against a plain simulation
+of that rule written here, and its choices against chunks measured on
+MI355X (faster: 96 at 224^3 and 64 at 320^3 and 448^3 in float64, 48 at
+224^3 and 96 at 448^3 in float32)."""
+import heapq
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2502_09537_amd", "csrc")
+ITEM = 17
+
+
+@pytest.fixture(scope="module")
+def driver(tmp_path_factory):
+    if shutil.which("g++") is None:
+        pytest.skip("needs g++")
+    exe = str(tmp_path_factory.mktemp("plan") / "plan_driver")
+    cmd = ["g++", "-O2", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include",
+           "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", exe,
+           os.path.join(ROOT, "tests", "plan", "plan_driver.cpp"),
+           os.path.join(CSRC, "kgs_stream3d_plan.cpp")]
+    subprocess.run(cmd, check=True, capture_output=True, text=True, timeout=300)
+
+    def run(tx, ty, cus, chunk, sizes):
+        out = subprocess.run([exe, str(tx), str(ty), str(cus), str(chunk), *map(str, sizes)],
+                             check=True, capture_output=True, text=True, timeout=60).stdout.split()
+        return int(out[0]), float(out[1]), int(out[2]), int(out[3])
+    return run
+
+
+def simulate(tx, ty, cus, chunk, sizes):
+    """The dealing rule, item by item."""
+    lens = []
+    for n in sizes:
+        tiles = ((n // 2 + tx - 1) // tx) * ((n + ty - 1) // ty)
+        for z0 in range(0, n, chunk):
+            lens += [min(chunk, n - z0) + ITEM] * tiles
+    items = len(lens)
+    groups = 8 if cus % 8 == 0 else 1
+    per = cus // groups
+    end = 0
+    for x in range(groups):
+        if groups == 1:
+            mine = lens
+        elif items % 8 == 0:
+            mine = lens[x * items // 8:(x + 1) * items // 8]
+        else:
+            mine = lens[x::8]
+        free = [0] * per
+        for L in mine:
+            t = heapq.heappop(free) + L
+            heapq.heappush(free, t)
+            end = max(end, t)
+    return end
+
+
+def test_whole_rounds_closed_form(driver):
+    # 256^3, 16x16 tiles: 128 tiles; chunk 128 -> 256 items, one round
+    assert driver(16, 16, 256, 128, [256])[1] == 128 + ITEM
+    # chunk 64 -> 512 items, two rounds of 64-plane items
+    assert driver(16, 16, 256, 64, [256])[1] == 2 * (64 + ITEM)
+    # chunk 32 -> 1024 items, four rounds
+    assert driver(16, 16, 256, 32, [256])[1] == 4 * (32 + ITEM)
+    # fewer items than CUs: the longest item
+    assert driver(16, 16, 256, 128, [64])[1] == 64 + ITEM
+
+
+@pytest.mark.parametrize("tx,ty,cus,chunk,sizes", [
+    (16, 16, 256, 96, [224]),            # 294 items: dealt to XCDs one by one
+    (16, 16, 256, 64, [224]),            # 392 items: contiguous eighths
+    (16, 32, 256, 48, [224, 96, 130]),
+    (16, 16, 64, 24, [70, 34, 200, 32]),
+    (16, 16, 100, 16, [90, 40]),         # CUs not a multiple of 8: one queue
+    (8, 8, 256, 12, [40, 66, 18]),
+])
+def test_estimate_equals_plain_simulation(driver, tx, ty, cus, chunk, sizes):
+    assert driver(tx, ty, cus, chunk, sizes)[1] == simulate(tx, ty, cus, chunk, sizes)
+
+
+def test_many_items_use_work_over_cus(driver):
+    # beyond 16384 items: total steps over the CUs plus one item
+    n = 1024
+    tiles = (n // 2 // 16) * (n // 16)
+    work = tiles * (n + (n // 8) * ITEM)
+    assert driver(16, 16, 256, 8, [n])[1] == pytest.approx(work / 256 + 8 + ITEM)
+
+
+@pytest.mark.parametrize("ty,n,best", [
+    (16, 256, 128), (16, 224, 96), (16, 320, 64), (16, 448, 64), (16, 128, 16), (16, 96, 8),
+    (32, 256, 64), (32, 224, 48), (32, 448, 96), (32, 512, 128),
+])
+def test_chosen_chunks(driver, ty, n, best):
+    assert driver(16, ty, 256, 0, [n])[0] == best
+
+
+def test_chosen_chunk_is_the_fastest_estimate(driver):
+    sizes = [64, 96, 128, 160, 192, 224, 256, 130, 200, 98]
+    best = driver(16, 16, 256, 0, sizes)[0]
+    est = {c: simulate(16, 16, 256, c, sizes) for c in (128, 96, 64, 48, 32, 24, 16, 12, 8)}
+    assert est[best] <= min(est.values()) / 0.99
+    # list launches: the precision's tile (16x16 float64, 16x32 float32)
+    _, _, l64, l32 = driver(16, 16, 256, 0, sizes)
+    assert l64 == best and l32 == driver(16, 32, 256, 0, sizes)[0]
