@@ -317,7 +317,11 @@ const char *kgs_batch_last_error(const kgs_batch *b);
  * per launch, the rest in one
  * batched launch sequence).  A request that arrives while
  * others run joins at the next round.  Finished requests are retired to host
- * memory and their device memory returns to the server's pool.  A freed
+ * memory and their device memory returns to the server's pool.  Host copies
+ * of inputs and results are pinned (one transfer each at the full link
+ * rate); the server keeps its pinned blocks for reuse and returns them to
+ * the system in kgs_server_free (pinning is capped at a quarter of the
+ * host's memory, at most 64 GiB; beyond it, plain host memory).  A freed
  * server's streams are kept and given to the next server created on the
  * same device (a server made with new streams after other device work can
  * run markedly slower).  Host code
