@@ -91,9 +91,15 @@ typedef struct {
 int kgs_init(const kgs_config *cfg, const double *psi_re, const double *psi_im, const double *u,
              const double *v_t, int32_t mem, void *stream, kgs_sim **out);
 
-/* Enqueue nsteps DP-AVF2 steps (nsteps >= 0; 0 does nothing).  On return of
- * the enqueued work the state is at a full-step boundary.  Asynchronous:
- * returns once the kernels are launched (KGS_EINVAL for nsteps < 0). */
+/* Enqueue nsteps DP-AVF2 steps (nsteps >= 0; 0 does nothing).  Asynchronous:
+ * returns once the kernels are launched (KGS_EINVAL for nsteps < 0).  The
+ * adjoint red sweep that closes the last step (Algorithm 3: a step ends with
+ * the red points of the adjoint half) may be left pending: the next
+ * kgs_step fuses it with its first red sweep, as consecutive steps within
+ * one call are fused, and every call that reads or replaces the state
+ * (kgs_energy, kgs_read_state, kgs_write_state, batches, kgs_autotune)
+ * applies it first.  What any call observes is bitwise the state after
+ * nsteps full steps. */
 int kgs_step(kgs_sim *sim, int64_t nsteps);
 
 /* Discrete energy of the current state: h^dim times E_h of sec. 2,

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include "kgs_trace.h"
+#include "kgs_energy.h"
 #include "kgs_internal.h"
 #include "kgs_plan.h"
 #include "kgs_sim.h"
@@ -304,6 +305,7 @@ int load_state(kgs_sim *s, const double *P, const double *Q, const double *U, co
     const int64_t npts = 2 * s->geo.count;
     const size_t bytes = static_cast<size_t>(npts) * sizeof(double);
     hipError_t e;
+    s->open = false;  // the state is replaced
     if (mem == KGS_DEVICE) {
         e = kgs::launch_scatter(s->geo, s->cfg.precision, s->state, P, Q, U, V, s->stream);
         if (e != hipSuccess) return hip_fail(s, e, "scatter kernel");
@@ -487,6 +489,17 @@ int sim_create_pooled(const kgs_config *cfg, const double *P, const double *Q, c
 
 int default_kernel(const kgs_config &cfg) { return default_tuning(cfg, false).kernel; }
 
+int sim_close(kgs_sim *s, hipStream_t stream)
+{
+    if (!s->open) return KGS_OK;
+    const int block = s->tuning.block > 0 ? s->tuning.block : 256;
+    const hipError_t e =
+        launch_sweep(s->geo, s->cfg.precision, s->state, PASS_R_ADJ, s->coef, block, stream);
+    if (e != hipSuccess) return hip_fail(s, e, "closing sweep launch");
+    s->open = false;
+    return KGS_OK;
+}
+
 kgs_tuning default_tuning_of(const kgs_config &cfg) { return default_tuning(cfg); }
 
 int64_t state_bytes(const kgs_config &cfg)
@@ -570,6 +583,7 @@ int step_fields_run(const kgs_config *cfg, double *P, double *Q, double *U, doub
     e = kgs::launch_scatter(s.geo, cfg->precision, s.state, P, Q, U, V, stream);
     if (e != hipSuccess) return set_error(hip_fail(&s, e, "scatter kernel"), s.err);
     rc = kgs_step(&s, nsteps);
+    if (rc == KGS_OK) rc = sim_close(&s, stream);
     if (rc != KGS_OK) return set_error(rc, s.err);
     e = kgs::launch_gather(s.geo, cfg->precision, s.state, P, Q, U, V, stream);
     if (e != hipSuccess) return set_error(hip_fail(&s, e, "gather kernel"), s.err);
@@ -650,7 +664,9 @@ int kgs_step(kgs_sim *s, int64_t nsteps)
         return e == hipSuccess ? KGS_OK : hip_fail(s, e, "sweep kernel launch");
     };
     if (s->tuning.kernel == KGS_KERNEL_RESIDENT) {
-        // one launch per run of at most kResidentRun steps
+        // one launch per run of at most kResidentRun steps, each closing its
+        // last step
+        if ((rc = kgs::sim_close(s, s->stream)) != KGS_OK) return rc;
         kgs::ResidentMember m;
         std::memset(&m, 0, sizeof(m));
         m.state = s->state;
@@ -669,9 +685,11 @@ int kgs_step(kgs_sim *s, int64_t nsteps)
     }
     if (s->tuning.kernel == KGS_KERNEL_STREAM || s->tuning.kernel == KGS_KERNEL_TILE) {
         // launches of 1 or 2 full steps (R, B[, R, B]) from one buffer to the
-        // other; the adjoint red sweep that closes the last step runs in place
+        // other; a pending adjoint red sweep of the previous call fuses with
+        // the first red sweep (R_ADJ_BASE instead of R_BASE), and the one
+        // that closes this call's last step is left pending
         const kgs::StreamShape sh = stream_shape(s);
-        bool first = true;
+        bool first = !s->open;
         for (int64_t left = nsteps; left > 0 && rc == KGS_OK;) {
             // steps of this launch: steps_per_launch while they last, then 2
             // or 1 (the tiled kernel takes 1, 2 or 4 per launch)
@@ -700,17 +718,19 @@ int kgs_step(kgs_sim *s, int64_t nsteps)
             if (e != hipSuccess) return hip_fail(s, e, "stream kernel launch");
             std::swap(s->state, s->state2);
             first = false;
+            s->open = true;
             left -= st;
         }
-        return sweep(kgs::PASS_R_ADJ);
+        return KGS_OK;
     }
-    rc = sweep(kgs::PASS_R_BASE);
+    // one colour sweep per launch, with the same pending closing sweep
+    rc = sweep(s->open ? kgs::PASS_R_ADJ_BASE : kgs::PASS_R_BASE);
     for (int64_t i = 1; i < nsteps && rc == KGS_OK; ++i) {
         rc = sweep(kgs::PASS_B_FULL);
         if (rc == KGS_OK) rc = sweep(kgs::PASS_R_ADJ_BASE);
     }
     if (rc == KGS_OK) rc = sweep(kgs::PASS_B_FULL);
-    if (rc == KGS_OK) rc = sweep(kgs::PASS_R_ADJ);
+    if (rc == KGS_OK) s->open = true;
     return rc;
 }
 
@@ -722,9 +742,20 @@ int kgs_energy(kgs_sim *s, double *energy)
     int rc = check_device(s);
     if (rc != KGS_OK) return rc;
     double *out = s->partials + 2 * kgs::energy_partial_slots();
-    hipError_t e = kgs::launch_energy(s->geo, s->cfg.precision, s->state, s->ecoef, s->partials,
-                                      out, s->stream);
-    if (e != hipSuccess) return hip_fail(s, e, "energy kernel launch");
+    hipError_t e = hipErrorNotSupported;
+    if (s->open) {
+        // the pending closing sweep and the energy in one pass
+        e = kgs::launch_energy_closing(s->geo, s->cfg.precision, s->state, s->ecoef, s->coef,
+                                       s->partials, out, s->stream);
+        if (e == hipSuccess) s->open = false;
+        else if (e != hipErrorNotSupported) return hip_fail(s, e, "energy kernel launch");
+    }
+    if (e == hipErrorNotSupported) {
+        if ((rc = kgs::sim_close(s, s->stream)) != KGS_OK) return rc;
+        e = kgs::launch_energy(s->geo, s->cfg.precision, s->state, s->ecoef, s->partials, out,
+                               s->stream);
+        if (e != hipSuccess) return hip_fail(s, e, "energy kernel launch");
+    }
     e = hipMemcpyAsync(s->host_out, out, 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream);
     if (e != hipSuccess) return hip_fail(s, e, "hipMemcpyAsync (energy)");
     e = hipStreamSynchronize(s->stream);
@@ -742,6 +773,7 @@ int kgs_read_state(kgs_sim *s, double *P, double *Q, double *U, double *V, int32
     if (mem != KGS_HOST && mem != KGS_DEVICE)
         return fail(s, KGS_EINVAL, "mem must be KGS_HOST or KGS_DEVICE");
     int rc = check_device(s);
+    if (rc == KGS_OK) rc = kgs::sim_close(s, s->stream);
     if (rc != KGS_OK) return rc;
     const int64_t npts = 2 * s->geo.count;
     const size_t bytes = static_cast<size_t>(npts) * sizeof(double);

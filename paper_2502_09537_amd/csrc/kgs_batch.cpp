@@ -313,6 +313,10 @@ int begin(kgs_batch *b)
     if (e != hipSuccess) return bhip(b, e, "hipGetDevice");
     if (dev != b->device && (e = hipSetDevice(b->device)) != hipSuccess)
         return bhip(b, e, "hipSetDevice");
+    // members left open by kgs_step get their closing sweep first, ordered
+    // like the batch's own work
+    for (kgs_sim *x : b->sims)
+        if (kgs::sim_close(x, b->user) != KGS_OK) return bfail(b, KGS_EDEVICE, x->err.c_str());
     if ((e = hipEventRecord(b->ev_in, b->user)) != hipSuccess) return bhip(b, e, "hipEventRecord");
     if ((e = hipStreamWaitEvent(b->own, b->ev_in, 0)) != hipSuccess)
         return bhip(b, e, "hipStreamWaitEvent");

@@ -1,7 +1,7 @@
 // Discrete energy E_h of sec. 2 (without the h^dim factor, which the host
 // applies): a deterministic, compensated float64 reduction.
 //
-// Each thread sums the energy density of its points into a double-double
+// Each thread sums the energy of its points into a double-double
 // (TwoSum), a wavefront of 64 lanes combines its lanes with shuffles in a
 // fixed tree, the waves of a workgroup combine through LDS in a fixed order,
 // and one final workgroup combines the per-workgroup partials in a fixed
@@ -10,18 +10,26 @@
 //
 // 2-D and 3-D grids stream along axis 0: a thread owns one column (a row
 // position along the other axes and a compressed x position, both colours)
-// and walks it through a chunk of consecutive planes of axis 0.  The forward
-// neighbour along axis 0 of a point is the other colour at the same column
-// in the next plane, which the thread loads anyway as its next plane's own
-// values, so the state is read from memory about once; the forward
-// neighbours along the other axes are other columns of the same plane
-// (cache hits).  1-D grids keep one thread per position.
+// and walks it through a chunk of consecutive planes of axis 0.  The energy
+// is summed edge by edge: on the checkerboard every edge of the grid joins a
+// red and a blue point, so the red point of a column takes the squared
+// differences to all of its 2*dim blue neighbours and both points add their
+// own terms.  These are the blue neighbours that the adjoint red sweep
+// reads, so the same pass can first apply the sweep that closes a step
+// (energy_closing_kernel): it rewrites only red points, each from its own
+// old values, which no other thread reads, so it runs in place.  The blue
+// neighbours along axis 0 are the thread's own column one plane back and
+// ahead (registers), the other ones are other columns of the same plane
+// (cache hits).  1-D grids keep one thread per position and forward
+// differences.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 
+#include "kgs_energy.h"
 #include "kgs_internal.h"
 #include "kgs_layout.h"
+#include "kgs_point.h"
 
 namespace kgs {
 namespace {
@@ -164,93 +172,48 @@ energy_partial_kernel(const T *__restrict__ base, int64_t stride, int n, int64_t
     }
 }
 
-// Energy density of one point from its own values (p, q, u, v) and the
-// other colour's forward neighbours: (P, Q) and U along axis 0, axis 1 (3-D
-// only) and x, in that order (the order of density()).
-template <int DIM>
-__device__ __forceinline__ double density_from(double p, double q, double u, double v,
-                                               const double (&nb)[3][3], const EnergyCoef &k)
-{
-    double gp = 0.0, gq = 0.0, gu = 0.0;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        const double dp = nb[a][0] - p;
-        const double dq = nb[a][1] - q;
-        const double du = nb[a][2] - u;
-        gp = gp + dp * dp;
-        gq = gq + dq * dq;
-        gu = gu + du * du;
-    }
-    return 0.5 * (k.k1_h2 * (gp + gq) + k.k2_h2 * gu + v * v + k.mu2 * (u * u)) -
-           k.gamma * (p * p + q * q) * u;
-}
+// (P, Q, U, V) of one point, and (P, Q, U) of a neighbour, as float64.
+struct Pt {
+    double p, q, u, v;
+};
 
-template <typename T>
-struct Col {
-    double p[2], q[2], u[2], v[2];  // per colour
+struct Nb {
+    double p, q, u;
 };
 
 template <typename T>
-__device__ __forceinline__ Col<T> load_column(const T *__restrict__ base, int64_t stride,
-                                              int64_t i)
+__device__ __forceinline__ Pt load_pt(const T *__restrict__ pq, const T *__restrict__ uv, int64_t i)
 {
-    Col<T> x;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const Pair<T> pq = ld_pair(pair_plane(base, stride, c, PAIR_PQ), i);
-        const Pair<T> uv = ld_pair(pair_plane(base, stride, c, PAIR_UV), i);
-        x.p[c] = pq.x;
-        x.q[c] = pq.y;
-        x.u[c] = uv.x;
-        x.v[c] = uv.y;
-    }
-    return x;
+    const Pair<T> a = ld_pair(pq, i), b = ld_pair(uv, i);
+    return Pt{static_cast<double>(a.x), static_cast<double>(a.y), static_cast<double>(b.x),
+              static_cast<double>(b.y)};
 }
 
-// The other colour's forward neighbours in one plane that the own column
-// does not hold: along axis 1 for both colours (3-D), and along x for the
-// colour whose x neighbour is the next compressed position.
 template <typename T>
+__device__ __forceinline__ Nb load_nb(const T *__restrict__ pq, const T *__restrict__ uv, int64_t j)
+{
+    const Pair<T> a = ld_pair(pq, j);
+    return Nb{static_cast<double>(a.x), static_cast<double>(a.y),
+              static_cast<double>(ld_global(uv + 2 * j))};
+}
+
+// The in-plane blue neighbours of a red point: axis 1 -, + (3-D) and x -, +.
 struct PlaneNb {
-    double a1[2][3];  // axis 1, per colour: P, Q, U of the other colour
-    double x[3];      // x, for the colour with offset 1
+    Nb y_m, y_p, x_m, x_p;
 };
-
-template <int DIM, typename T>
-__device__ __forceinline__ PlaneNb<T> load_plane_nb(const T *__restrict__ base, int64_t stride,
-                                                    int64_t plane, int64_t fwd1, int64_t xrow,
-                                                    int z, int i1)
-{
-    PlaneNb<T> nb;
-    if (DIM == 3) {
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int oc = c ^ 1;
-            const int64_t j = plane + fwd1;
-            const Pair<T> pq = ld_pair(pair_plane(base, stride, oc, PAIR_PQ), j);
-            nb.a1[c][0] = pq.x;
-            nb.a1[c][1] = pq.y;
-            nb.a1[c][2] = static_cast<double>(ld_global(pair_plane(base, stride, oc, PAIR_UV) + 2 * j));
-        }
-    }
-    // colour c has x offset (s + DIM + 1 + c) & 1; offset 1 for c = (s + DIM) & 1
-    const int s = DIM == 3 ? z + i1 : z;
-    const int oc = ((s + DIM) & 1) ^ 1;
-    const int64_t j = plane + xrow;
-    const Pair<T> pq = ld_pair(pair_plane(base, stride, oc, PAIR_PQ), j);
-    nb.x[0] = pq.x;
-    nb.x[1] = pq.y;
-    nb.x[2] = static_cast<double>(ld_global(pair_plane(base, stride, oc, PAIR_UV) + 2 * j));
-    return nb;
-}
 
 // Workgroup (blockIdx.x, blockIdx.y): columns [256 blockIdx.x, +256) of a
-// plane (cols per plane: n/2 in 2-D, n * n/2 in 3-D) and planes
-// [chunk * blockIdx.y, +chunk) of axis 0.  Loads run ahead of their use:
-// the own column two planes ahead, the in-plane neighbours one plane ahead.
-template <int DIM, typename T>
+// plane (columns per plane: n/2 in 2-D, n * n/2 in 3-D) and planes
+// [chunk * blockIdx.y, +chunk) of axis 0.  Per plane a thread adds, in this
+// order: the red point's squared differences to its blue neighbours (axis 0
+// -, +, axis 1 -, + in 3-D, x -, +) with its own terms, then the blue
+// point's own terms.  With CLOSE the red point first takes the adjoint red
+// sweep (the neighbour sums in the order of the sweep kernels, so the state
+// is bitwise that of the sweep) and is stored; its energy uses the stored
+// values.  Loads run one plane ahead of their use.
+template <int DIM, typename T, bool CLOSE>
 __global__ void __launch_bounds__(kBlock)
-energy_stream_kernel(const T *__restrict__ base, int64_t stride, int n, int chunk, EnergyCoef k,
+energy_stream_kernel(T *__restrict__ base, int64_t stride, int n, int chunk, EnergyCoef k, Coef kc,
                      double *__restrict__ partials)
 {
     const int H = n >> 1;
@@ -260,52 +223,96 @@ energy_stream_kernel(const T *__restrict__ base, int64_t stride, int n, int chun
     const int z1 = min(n, z0 + chunk);
     DD acc = {0.0, 0.0};
     if (col < cols) {
+        T *rpq = pair_plane(base, stride, RED, PAIR_PQ), *ruv = pair_plane(base, stride, RED, PAIR_UV);
+        const T *bpq = pair_plane(base, stride, BLUE, PAIR_PQ);
+        const T *buv = pair_plane(base, stride, BLUE, PAIR_UV);
         const int i1 = DIM == 3 ? static_cast<int>(col / H) : 0;
         const int xh = static_cast<int>(col - static_cast<int64_t>(i1) * H);
-        const int xn = xh + 1 == H ? 0 : xh + 1;
-        // columns of the forward neighbours inside a plane: the next row
-        // along axis 1 (3-D) and the next compressed x position
-        const int64_t fwd1 = DIM == 3 ? static_cast<int64_t>(i1 == n - 1 ? 0 : i1 + 1) * H + xh : 0;
-        const int64_t xrow = static_cast<int64_t>(i1) * H + xn;
-        auto wrapz = [&](int z) { return z >= n ? z - n : z; };
-        Col<T> cur = load_column(base, stride, static_cast<int64_t>(z0) * cols + col);
-        Col<T> nxt = load_column(base, stride, static_cast<int64_t>(wrapz(z0 + 1)) * cols + col);
-        PlaneNb<T> nbc = load_plane_nb<DIM>(base, stride, static_cast<int64_t>(z0) * cols, fwd1,
-                                            xrow, z0, i1);
-        for (int z = z0; z < z1; ++z) {
-            Col<T> nn = nxt;
-            PlaneNb<T> nbn = nbc;
-            if (z + 1 < z1) {
-                nn = load_column(base, stride, static_cast<int64_t>(wrapz(z + 2)) * cols + col);
-                nbn = load_plane_nb<DIM>(base, stride, static_cast<int64_t>(z + 1) * cols, fwd1,
-                                         xrow, z + 1, i1);
-            }
+        const int xhm = xh == 0 ? H - 1 : xh - 1, xhp = xh + 1 == H ? 0 : xh + 1;
+        const int64_t row = static_cast<int64_t>(i1) * H;  // first column of this row in a plane
+        const int64_t ym = DIM == 3 ? static_cast<int64_t>(i1 == 0 ? n - 1 : i1 - 1) * H + xh : 0;
+        const int64_t yp = DIM == 3 ? static_cast<int64_t>(i1 == n - 1 ? 0 : i1 + 1) * H + xh : 0;
+        auto wrapz = [&](int z) { return z < 0 ? z + n : z >= n ? z - n : z; };
+        auto plane_nb = [&](int z) {
+            const int64_t pl = static_cast<int64_t>(z) * cols;
             const int s = DIM == 3 ? z + i1 : z;
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const int o = (s + DIM + 1 + c) & 1;  // x = 2 xh + o for colour c
-                const int oc = c ^ 1;
-                double nb[3][3];
-                // axis 0: the other colour at this column of the next plane
-                nb[0][0] = nxt.p[oc];
-                nb[0][1] = nxt.q[oc];
-                nb[0][2] = nxt.u[oc];
-                int a = 1;
-                if (DIM == 3) {
-                    nb[1][0] = nbc.a1[c][0];
-                    nb[1][1] = nbc.a1[c][1];
-                    nb[1][2] = nbc.a1[c][2];
-                    a = 2;
-                }
-                // x: the other colour at compressed position xh + o
-                nb[a][0] = o ? nbc.x[0] : cur.p[oc];
-                nb[a][1] = o ? nbc.x[1] : cur.q[oc];
-                nb[a][2] = o ? nbc.x[2] : cur.u[oc];
-                acc = dd_add(acc, density_from<DIM>(cur.p[c], cur.q[c], cur.u[c], cur.v[c], nb, k));
+            const int o = (s + DIM + 1 + RED) & 1;  // red point at x = 2 xh + o
+            PlaneNb nb;
+            if (DIM == 3) {
+                nb.y_m = load_nb(bpq, buv, pl + ym);
+                nb.y_p = load_nb(bpq, buv, pl + yp);
             }
-            cur = nxt;
-            nxt = nn;
-            nbc = nbn;
+            nb.x_m = load_nb(bpq, buv, pl + row + (o ? xh : xhm));
+            nb.x_p = load_nb(bpq, buv, pl + row + (o ? xhp : xh));
+            return nb;
+        };
+        auto blue_at = [&](int z) { return load_pt(bpq, buv, static_cast<int64_t>(wrapz(z)) * cols + col); };
+        Pt b_m = blue_at(z0 - 1), b_0 = blue_at(z0), b_p = blue_at(z0 + 1);
+        Pt r_0 = load_pt(rpq, ruv, static_cast<int64_t>(z0) * cols + col);
+        PlaneNb nb_0 = plane_nb(z0);
+        for (int z = z0; z < z1; ++z) {
+            Pt b_pp = b_p, r_1 = r_0;
+            PlaneNb nb_1 = nb_0;
+            if (z + 1 < z1) {
+                b_pp = blue_at(z + 2);
+                r_1 = load_pt(rpq, ruv, static_cast<int64_t>(z + 1) * cols + col);
+                nb_1 = plane_nb(z + 1);
+            }
+            double pr = r_0.p, pi = r_0.q, u = r_0.u, v = r_0.v;
+            if (CLOSE) {
+                double sr = b_m.p, si = b_m.q, su = b_m.u;
+                sr = sr + b_p.p;
+                si = si + b_p.q;
+                su = su + b_p.u;
+                if (DIM == 3) {
+                    sr = sr + nb_0.y_m.p;
+                    si = si + nb_0.y_m.q;
+                    su = su + nb_0.y_m.u;
+                    sr = sr + nb_0.y_p.p;
+                    si = si + nb_0.y_p.q;
+                    su = su + nb_0.y_p.u;
+                }
+                sr = sr + nb_0.x_m.p;
+                si = si + nb_0.x_m.q;
+                su = su + nb_0.x_m.u;
+                sr = sr + nb_0.x_p.p;
+                si = si + nb_0.x_p.q;
+                su = su + nb_0.x_p.u;
+                sweep_point<PASS_R_ADJ, T>(kc, pr, pi, u, v, sr, si, su);
+                const T tp = static_cast<T>(pr), tq = static_cast<T>(pi);
+                const T tu = static_cast<T>(u), tv = static_cast<T>(v);
+                const int64_t i = static_cast<int64_t>(z) * cols + col;
+                st_pair(rpq, i, tp, tq);
+                st_pair(ruv, i, tu, tv);
+                pr = tp;
+                pi = tq;
+                u = tu;
+                v = tv;
+            }
+            double gp = 0.0, gq = 0.0, gu = 0.0;
+            auto edge = [&](double bp, double bq, double bu) {
+                const double dp = bp - pr, dq = bq - pi, du = bu - u;
+                gp = gp + dp * dp;
+                gq = gq + dq * dq;
+                gu = gu + du * du;
+            };
+            edge(b_m.p, b_m.q, b_m.u);
+            edge(b_p.p, b_p.q, b_p.u);
+            if (DIM == 3) {
+                edge(nb_0.y_m.p, nb_0.y_m.q, nb_0.y_m.u);
+                edge(nb_0.y_p.p, nb_0.y_p.q, nb_0.y_p.u);
+            }
+            edge(nb_0.x_m.p, nb_0.x_m.q, nb_0.x_m.u);
+            edge(nb_0.x_p.p, nb_0.x_p.q, nb_0.x_p.u);
+            acc = dd_add(acc, 0.5 * (k.k1_h2 * (gp + gq) + k.k2_h2 * gu + v * v + k.mu2 * (u * u)) -
+                                  k.gamma * (pr * pr + pi * pi) * u);
+            acc = dd_add(acc, 0.5 * (b_0.v * b_0.v + k.mu2 * (b_0.u * b_0.u)) -
+                                  k.gamma * (b_0.p * b_0.p + b_0.q * b_0.q) * b_0.u);
+            b_m = b_0;
+            b_0 = b_p;
+            b_p = b_pp;
+            r_0 = r_1;
+            nb_0 = nb_1;
         }
     }
     acc = block_reduce(acc);
@@ -333,45 +340,68 @@ energy_final_kernel(const double *__restrict__ partials, int nparts, double *__r
 
 int energy_partial_slots() { return kSlots; }
 
+namespace {
+
+// The streaming launch shape of a 2-D or 3-D grid: workgroups of kBlock
+// columns of a plane of axis 0 (bx) by chunks of planes long enough for
+// about 2^18 threads in all but no shorter than needed to keep the
+// workgroups within kSlots.  False when the grid does not stream (1-D, or
+// more than kSlots workgroups of columns per plane).
+bool stream_shape(const Geometry &g, int64_t &bx, int64_t &by, int64_t &chunk)
+{
+    if (g.dim < 2) return false;
+    const int64_t cols = g.dim == 3 ? static_cast<int64_t>(g.n) * (g.n / 2) : g.n / 2;
+    bx = (cols + kBlock - 1) / kBlock;
+    if (bx > kSlots) return false;
+    chunk = std::max<int64_t>(1, std::min<int64_t>(32, cols * g.n / (1 << 18)));
+    while (bx * ((g.n + chunk - 1) / chunk) > kSlots) ++chunk;
+    by = (g.n + chunk - 1) / chunk;
+    return true;
+}
+
+bool geometry_ok(const Geometry &g)
+{
+    return g.dim >= 1 && g.dim <= 3 && g.n >= 2 && !(g.n & 1) && g.count > 0 && g.stride >= g.count;
+}
+
+template <bool CLOSE>
+hipError_t launch_stream(const Geometry &g, int precision, void *state, const EnergyCoef &k,
+                         const Coef &kc, double *partials, double *out, hipStream_t s)
+{
+    int64_t bx = 0, by = 0, chunk = 0;
+    if (!stream_shape(g, bx, by, chunk)) return hipErrorNotSupported;
+    const dim3 grid2(static_cast<unsigned>(bx), static_cast<unsigned>(by));
+#define KGS_ENERGY_S(D, T)                                                                      \
+    hipLaunchKernelGGL((energy_stream_kernel<D, T, CLOSE>), grid2, dim3(kBlock), 0, s,          \
+                       static_cast<T *>(state), g.stride, g.n, static_cast<int>(chunk), k, kc,  \
+                       partials)
+    if (precision == 0) {
+        if (g.dim == 2) KGS_ENERGY_S(2, double);
+        else KGS_ENERGY_S(3, double);
+    } else {
+        if (g.dim == 2) KGS_ENERGY_S(2, float);
+        else KGS_ENERGY_S(3, float);
+    }
+#undef KGS_ENERGY_S
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(kBlock), 0, s, partials,
+                       static_cast<int>(bx * by), out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_energy(const Geometry &g, int precision, const void *state,
                          const EnergyCoef &k, double *partials, double *out, hipStream_t s)
 {
-    if (!state || !partials || !out || g.dim < 1 || g.dim > 3 || g.n < 2 || (g.n & 1) ||
-        g.count <= 0 || g.stride < g.count)
-        return hipErrorInvalidValue;
+    if (!state || !partials || !out || !geometry_ok(g)) return hipErrorInvalidValue;
+    // the streaming kernel only reads the state without CLOSE
+    hipError_t e = launch_stream<false>(g, precision, const_cast<void *>(state), k, Coef{},
+                                        partials, out, s);
+    if (e != hipErrorNotSupported) return e;
     int64_t blocks = (g.count + kBlock - 1) / kBlock;
     if (blocks > kSlots) blocks = kSlots;
-    // 2-D and 3-D: columns of a plane of axis 0 in workgroups of kBlock,
-    // and chunks of planes long enough for about 2^18 threads in all but no
-    // shorter than needed to keep the workgroups within kSlots (grids with
-    // more than kSlots workgroups of columns per plane use one thread per
-    // position instead)
-    const int64_t cols = g.dim == 3 ? static_cast<int64_t>(g.n) * (g.n / 2) : g.n / 2;
-    const int64_t bx = (cols + kBlock - 1) / kBlock;
-    if (g.dim >= 2 && bx <= kSlots) {
-        int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(32, cols * g.n / (1 << 18)));
-        while (bx * ((g.n + chunk - 1) / chunk) > kSlots) ++chunk;
-        const int64_t by = (g.n + chunk - 1) / chunk;
-        blocks = bx * by;
-        const dim3 grid2(static_cast<unsigned>(bx), static_cast<unsigned>(by));
-#define KGS_ENERGY_S(D, T)                                                                      \
-    hipLaunchKernelGGL((energy_stream_kernel<D, T>), grid2, dim3(kBlock), 0, s,                 \
-                       static_cast<const T *>(state), g.stride, g.n, static_cast<int>(chunk), k, \
-                       partials)
-        if (precision == 0) {
-            if (g.dim == 2) KGS_ENERGY_S(2, double);
-            else KGS_ENERGY_S(3, double);
-        } else {
-            if (g.dim == 2) KGS_ENERGY_S(2, float);
-            else KGS_ENERGY_S(3, float);
-        }
-#undef KGS_ENERGY_S
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(kBlock), 0, s, partials,
-                           static_cast<int>(blocks), out);
-        return hipGetLastError();
-    }
     const dim3 grid(static_cast<unsigned>(blocks)), threads(kBlock);
 #define KGS_ENERGY(D, T)                                                                        \
     hipLaunchKernelGGL((energy_partial_kernel<D, T>), grid, threads, 0, s,                      \
@@ -386,11 +416,19 @@ hipError_t launch_energy(const Geometry &g, int precision, const void *state,
         else KGS_ENERGY(3, float);
     }
 #undef KGS_ENERGY
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(kBlock), 0, s, partials,
                        static_cast<int>(blocks), out);
     return hipGetLastError();
+}
+
+hipError_t launch_energy_closing(const Geometry &g, int precision, void *state,
+                                 const EnergyCoef &k, const Coef &kc, double *partials,
+                                 double *out, hipStream_t s)
+{
+    if (!state || !partials || !out || !geometry_ok(g)) return hipErrorInvalidValue;
+    return launch_stream<true>(g, precision, state, k, kc, partials, out, s);
 }
 
 }  // namespace kgs

@@ -965,7 +965,8 @@ int run_big(kgs_server *s)
             continue;
         }
         if (r->cfg.dim == 3 && r->sim->tuning.kernel == KGS_KERNEL_STREAM) {
-            if (kgs_step(r->sim, pk.second) != KGS_OK) {
+            if (kgs_step(r->sim, pk.second) != KGS_OK ||
+                kgs::sim_close(r->sim, r->sim->stream) != KGS_OK) {
                 r->status = KGS_EDEVICE;
                 r->err = kgs_last_error(r->sim);
             }

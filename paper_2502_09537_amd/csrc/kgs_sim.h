@@ -28,10 +28,17 @@ struct kgs_sim {
     int device = 0;
     kgs_tuning tuning;
     int64_t device_bytes = 0;
+    // the adjoint red sweep that closes the last step is still to be
+    // applied (kgs_step leaves it to the next step, which fuses it with its
+    // first red sweep, or to the next call that reads the state)
+    bool open = false;
     std::string err;
 };
 
 namespace kgs {
+
+// Applies a handle's pending adjoint red sweep (if any) on `stream`.
+int sim_close(kgs_sim *s, hipStream_t stream);
 
 // The first failure of a series of runtime calls that are all attempted,
 // such as the releases of every resource of an object, which continue after

@@ -241,6 +241,8 @@ extern "C" int kgs_autotune(kgs_sim *s, int32_t steps, int32_t use_cache, kgs_tu
         return KGS_ENOMEM;
     }
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) rc = KGS_EDEVICE;
+    // the state is saved closed and restored closed after every candidate
+    if (rc == KGS_OK && kgs::sim_close(s, s->stream) != KGS_OK) rc = KGS_EDEVICE;
     if (rc == KGS_OK &&
         hipMemcpyAsync(backup, s->state, bytes, hipMemcpyDeviceToDevice, s->stream) != hipSuccess)
         rc = KGS_EDEVICE;
@@ -274,6 +276,7 @@ extern "C" int kgs_autotune(kgs_sim *s, int32_t steps, int32_t use_cache, kgs_tu
                 rc = KGS_EDEVICE;
                 break;
             }
+            s->open = false;
         }
     }
     if (hipStreamSynchronize(s->stream) != hipSuccess && rc == KGS_OK) rc = KGS_EDEVICE;
