@@ -29,6 +29,7 @@
 #include "kgs_energy.h"
 #include "kgs_internal.h"
 #include "kgs_layout.h"
+#include "kgs_plan.h"
 #include "kgs_point.h"
 
 namespace kgs {
@@ -342,21 +343,14 @@ int energy_partial_slots() { return kSlots; }
 
 namespace {
 
-// The streaming launch shape of a 2-D or 3-D grid: workgroups of kBlock
-// columns of a plane of axis 0 (bx) by chunks of planes long enough for
-// about 2^18 threads in all but no shorter than needed to keep the
-// workgroups within kSlots.  False when the grid does not stream (1-D, or
-// more than kSlots workgroups of columns per plane).
+// The streaming launch shape of a 2-D or 3-D grid (energy_grid): the same
+// for the plain and the closing form, so both sum in the same order.  False
+// when the grid does not stream.  Measured on MI355X at 256^3 float64, the
+// closing form: 167 us with 768 workgroups (one round of three per CU)
+// against 179 us with 1024 (32 planes each).
 bool stream_shape(const Geometry &g, int64_t &bx, int64_t &by, int64_t &chunk)
 {
-    if (g.dim < 2) return false;
-    const int64_t cols = g.dim == 3 ? static_cast<int64_t>(g.n) * (g.n / 2) : g.n / 2;
-    bx = (cols + kBlock - 1) / kBlock;
-    if (bx > kSlots) return false;
-    chunk = std::max<int64_t>(1, std::min<int64_t>(32, cols * g.n / (1 << 18)));
-    while (bx * ((g.n + chunk - 1) / chunk) > kSlots) ++chunk;
-    by = (g.n + chunk - 1) / chunk;
-    return true;
+    return energy_grid(g.dim, g.n, device_cus(), &bx, &by, &chunk);
 }
 
 bool geometry_ok(const Geometry &g)

@@ -1,5 +1,6 @@
-// Launch planning for the z-streaming kernel (kgs_stream3d.hip): the plane
-// chunk whose launch is estimated to end first.
+// Launch planning: the plane chunk of z-streaming launches (kgs_stream3d.hip)
+// and the grid of the streaming energy reduction (kgs_energy.hip), each the
+// one estimated to end first.
 #include <algorithm>
 #include <cstdint>
 #include <functional>
@@ -79,6 +80,29 @@ int stream3d_chunk(const int *n, int count, int tile_x, int tile_y, int cus)
         }
     }
     return best;
+}
+
+bool energy_grid(int dim, int n, int cus, int64_t *bx, int64_t *by, int64_t *chunk)
+{
+    constexpr int kBlock = 256, kSlots = 2048, kResident = 3, kStartSteps = 2;
+    if (dim < 2 || n < 2 || cus < 1) return false;
+    const int64_t cols = dim == 3 ? static_cast<int64_t>(n) * (n / 2) : n / 2;
+    const int64_t x = (cols + kBlock - 1) / kBlock;
+    if (x > kSlots) return false;
+    const int64_t round = static_cast<int64_t>(kResident) * cus;
+    double best = -1.0;
+    for (int64_t b = 1; b <= n && x * b <= kSlots; ++b) {
+        const int64_t c = (n + b - 1) / b;
+        const int64_t y = (n + c - 1) / c;  // chunks of c planes actually needed
+        const double t = static_cast<double>((x * y + round - 1) / round) * (c + kStartSteps);
+        if (best < 0.0 || t < best) {
+            best = t;
+            *bx = x;
+            *by = y;
+            *chunk = c;
+        }
+    }
+    return best >= 0.0;
 }
 
 int stream3d_list_chunk(const int *n, int count, int elem_bytes)

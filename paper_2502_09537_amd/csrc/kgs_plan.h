@@ -1,5 +1,7 @@
-// Host-side launch planning (kgs_stream3d_plan.cpp, kgs_launch.cpp).
+// Host-side launch planning (kgs_plan.cpp, kgs_launch.cpp).
 #pragma once
+
+#include <cstdint>
 
 namespace kgs {
 
@@ -17,5 +19,13 @@ double stream3d_launch_steps(const int *n, int count, int tile_x, int tile_y, in
 // member-list launch of that precision on the current device.
 int stream3d_chunk(const int *n, int count, int tile_x, int tile_y, int cus);
 int stream3d_list_chunk(const int *n, int count, int elem_bytes);
+
+// Grid of the streaming energy reduction of a 2-D or 3-D grid (workgroups
+// of 256 columns of a plane of axis 0, bx per plane, by chunks of `chunk`
+// planes): the closing form holds three workgroups per CU, so the chunk is
+// the one that minimises whole rounds of 3 * cus workgroups times planes
+// per workgroup (plus 2 for its first loads).  False for 1-D grids and
+// planes of more than 2048 * 256 columns, which do not stream.
+bool energy_grid(int dim, int n, int cus, int64_t *bx, int64_t *by, int64_t *chunk);
 
 }  // namespace kgs

@@ -1,9 +1,11 @@
 // Prints the launch estimate and the chosen chunk of the z-streaming launch
 // planner for one group of grids: plan_driver tile_x tile_y cus chunk n...
-// (chunk 0: only the chosen chunk).  The planner's two device-facing
+// (chunk 0: only the chosen chunk); or the energy reduction's grid:
+// plan_driver energy dim n cus.  The planner's two device-facing
 // helpers are stood in for here: no GPU is needed.
 #include <cstdio>
 #include <cstdlib>
+#include <string>
 #include <vector>
 
 #include "kgs_plan.h"
@@ -19,6 +21,15 @@ int device_cus() { return 256; }
 
 int main(int argc, char **argv)
 {
+    if (argc == 5 && std::string(argv[1]) == "energy") {
+        // plan_driver energy dim n cus: bx by chunk (0 0 0: no streaming grid)
+        int64_t bx = 0, by = 0, chunk = 0;
+        const bool ok = kgs::energy_grid(std::atoi(argv[2]), std::atoi(argv[3]),
+                                         std::atoi(argv[4]), &bx, &by, &chunk);
+        std::printf("%lld %lld %lld\n", static_cast<long long>(ok ? bx : 0),
+                    static_cast<long long>(ok ? by : 0), static_cast<long long>(ok ? chunk : 0));
+        return 0;
+    }
     if (argc < 6) return 2;
     const int tx = std::atoi(argv[1]), ty = std::atoi(argv[2]), cus = std::atoi(argv[3]);
     const int chunk = std::atoi(argv[4]);

@@ -1,5 +1,5 @@
-"""CPU: the plane-chunk planner of the z-streaming launches
-(csrc/kgs_stream3d_plan.cpp).  A launch runs one workgroup per CU; its
+"""CPU: the launch planner (csrc/kgs_plan.cpp).  The plane-chunk planner of
+the z-streaming launches:  A launch runs one workgroup per CU; its
 workgroups are dealt to the 8 XCDs in turn and each XCD starts its next work
 item (a tile of one grid by a chunk of its z-planes) on its first free CU,
 an item of L planes taking L + 17 plane-steps.  The planner's estimate is
@@ -27,13 +27,19 @@ def driver(tmp_path_factory):
     cmd = ["g++", "-O2", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include",
            "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", exe,
            os.path.join(ROOT, "tests", "plan", "plan_driver.cpp"),
-           os.path.join(CSRC, "kgs_stream3d_plan.cpp")]
+           os.path.join(CSRC, "kgs_plan.cpp")]
     subprocess.run(cmd, check=True, capture_output=True, text=True, timeout=300)
 
     def run(tx, ty, cus, chunk, sizes):
         out = subprocess.run([exe, str(tx), str(ty), str(cus), str(chunk), *map(str, sizes)],
                              check=True, capture_output=True, text=True, timeout=60).stdout.split()
         return int(out[0]), float(out[1]), int(out[2]), int(out[3])
+
+    def energy(dim, n, cus):
+        out = subprocess.run([exe, "energy", str(dim), str(n), str(cus)], check=True,
+                             capture_output=True, text=True, timeout=60).stdout.split()
+        return tuple(int(v) for v in out)
+    run.energy = energy
     return run
 
 
@@ -110,3 +116,33 @@ def test_chosen_chunk_is_the_fastest_estimate(driver):
     # list launches: the precision's tile (16x16 float64, 16x32 float32)
     _, _, l64, l32 = driver(16, 16, 256, 0, sizes)
     assert l64 == best and l32 == driver(16, 32, 256, 0, sizes)[0]
+
+
+# The energy reduction's grid: workgroups of 256 columns of a plane of axis
+# 0; the closing form holds three per CU, so the planes per workgroup are
+# chosen to fill whole rounds of 3 * CUs workgroups (rounds x (planes + 2)).
+def energy_cost(dim, n, cus, by):
+    cols = n * (n // 2) if dim == 3 else n // 2
+    bx = -(-cols // 256)
+    c = -(-n // by)
+    y = -(-n // c)
+    return -(-(bx * y) // (3 * cus)) * (c + 2), bx, y, c
+
+
+@pytest.mark.parametrize("dim,n,cus", [(3, 256, 256), (3, 512, 256), (3, 96, 256), (3, 34, 256),
+                                       (2, 2048, 256), (2, 130, 256), (3, 256, 80), (3, 1024, 256)])
+def test_energy_grid_is_the_cheapest_shape(driver, dim, n, cus):
+    bx, by, chunk = driver.energy(dim, n, cus)
+    assert bx == -(-(n * (n // 2) if dim == 3 else n // 2) // 256)
+    assert bx * by <= 2048 and by == -(-n // chunk) and chunk * (by - 1) < n <= chunk * by
+    costs = [energy_cost(dim, n, cus, b)[0] for b in range(1, n + 1) if bx * b <= 2048]
+    assert energy_cost(dim, n, cus, by)[0] == min(costs)
+
+
+def test_energy_grid_cases(driver):
+    # 256^3 on 256 CUs: 768 workgroups of 43 planes, one round (measured on
+    # MI355X, closing form, float64: 167 us against 179 us for 1024
+    # workgroups of 32 planes)
+    assert driver.energy(3, 256, 256) == (128, 6, 43)
+    assert driver.energy(1, 1024, 256) == (0, 0, 0)      # 1-D: no streaming grid
+    assert driver.energy(3, 2048, 256) == (0, 0, 0)      # planes beyond 2048 x 256 columns
