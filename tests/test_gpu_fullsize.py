@@ -115,6 +115,40 @@ def test_3d_256_sampled_points_match_the_oracle(prec):
         oracle_check.compare(prec, got, *refs, label=f"block at {st}")
 
 
+@pytest.mark.parametrize("prec", [workloads.FP64, workloads.FP32])
+def test_3d_256_whole_grid_after_the_bench_sequence_matches_the_oracle(prec):
+    """The sequence bench.py times, at full size: kgs_step (4-sweep streaming
+    launches; the sweep that closes the last step is left pending), then
+    kgs_energy (that sweep and the reduction in one pass).  Every point of
+    the 256^3 grid after 4 steps against the all-cores oracle (bitwise the
+    one-core oracle), and the energy against the oracle's energy of the
+    state the GPU holds."""
+    import os
+
+    import oracle
+
+    steps = 4
+    p = workloads.random_problem(3, 256, seed=19, tau=0.002, amp=0.5, lo=-8.0, hi=8.0,
+                                 precision=prec)
+    say("3-D 256^3 x 4 steps + closing energy, whole grid vs oracle", prec)
+    sim = kgs.simulation_from_problem(p)
+    assert sim.info().kernel == kgs.KGS_KERNEL_STREAM
+    sim.step(steps)
+    e = sim.energy()
+    got = sim.read_state()
+    sim.close()
+    threads = max(1, min(16, os.cpu_count() or 1))
+    g = oracle_check.grid_of(p)
+    refs = []
+    for bits in ((64,) if prec == workloads.FP64 else (64, 32)):
+        r = oracle.State.from_fields(p.psi, p.u, p.v)
+        oracle.step_passes(g, p.tau, r, steps, storage_bits=bits, threads=threads)
+        refs.append((r.psi, r.U, r.V))
+    oracle_check.compare(prec, got, *refs, label="256^3 whole grid")
+    e_ref = oracle.energy(g, oracle.State.from_fields(*got))
+    assert abs(e - e_ref) <= 1e-13 * abs(e_ref), (e, e_ref)
+
+
 def sub_block_refs(g, tau, steps, prec, initial, c):
     """The float64 oracle (and, for a float32 state, its float32-storage
     mode) on a periodic sub-block from `initial` = (psi, u, v), restricted to
