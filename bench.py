@@ -254,7 +254,9 @@ def bench_batched(args):
     for mode in ("per_instance", "batched", "batched_graph", "batched_tuned"):
         sims = [kgs.simulation_from_problem(p) for p in probs]
         if mode == "per_instance":
-            run = lambda: [s.step(steps) for s in sims]
+            # each handle completes its steps (kgs_sync applies the closing
+            # sweep that kgs_step leaves pending), as a batched run does
+            run = lambda: [s.step(steps) for s in sims] + [s.sync() for s in sims]
         else:
             b = kgs.Batch(sims, graph=(mode != "batched"))
             if mode == "batched_tuned":
@@ -642,8 +644,10 @@ def main():
         reps.append(a.elapsed_time(b))
 
     # the dominant kernel's own average duration: a kgs_step call of K steps
-    # is K/spl streaming launches (or 2K sweeps) plus one closing sweep, so
-    # time 2- and 4-step calls and take the difference
+    # is K/spl streaming launches (or 2K sweeps); the sweep closing its last
+    # step is left pending and fused into the next call's first launch, and
+    # whatever fixed cost a call has besides cancels in the difference of
+    # 2- and 4-step calls
     def timed(k):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
@@ -656,7 +660,7 @@ def main():
     t_small = min(timed(2 * spl) for _ in range(3))
     t_big = min(timed(4 * spl) for _ in range(3))
     unit_ms = (t_big - t_small) / (2 * per)           # one dominant-kernel launch
-    closing_ms = max(t_small - 2 * per * unit_ms, 0.0)  # the closing sweep
+    closing_ms = max(t_small - 2 * per * unit_ms, 0.0)  # a call's fixed cost
     sim.close()
 
     updates = p.points * args.steps

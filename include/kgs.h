@@ -97,7 +97,8 @@ int kgs_init(const kgs_config *cfg, const double *psi_re, const double *psi_im, 
  * the red points of the adjoint half) may be left pending: the next
  * kgs_step fuses it with its first red sweep, as consecutive steps within
  * one call are fused, and every call that reads or replaces the state
- * (kgs_energy, kgs_read_state, kgs_write_state, batches, kgs_autotune)
+ * (kgs_energy, kgs_read_state, kgs_write_state, kgs_sync, batches,
+ * kgs_autotune)
  * applies it first.  What any call observes is bitwise the state after
  * nsteps full steps. */
 int kgs_step(kgs_sim *sim, int64_t nsteps);
@@ -124,7 +125,8 @@ int kgs_read_state(kgs_sim *sim, double *psi_re, double *psi_im, double *u, doub
 int kgs_write_state(kgs_sim *sim, const double *psi_re, const double *psi_im, const double *u,
                     const double *v_t, int32_t mem);
 
-/* Wait until all work enqueued for the handle has finished. */
+/* Complete the handle's steps (a pending closing sweep of the last step is
+ * applied) and wait until all work enqueued for it has finished. */
 int kgs_sync(kgs_sim *sim);
 
 /* Release the device state.  NULL is accepted.  Waits for the stream.  The

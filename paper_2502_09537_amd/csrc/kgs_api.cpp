@@ -815,6 +815,7 @@ int kgs_sync(kgs_sim *s)
     KGS_TRACE("kgs_sync");
     if (!s) return fail(nullptr, KGS_EINVAL, "handle is NULL");
     int rc = check_device(s);
+    if (rc == KGS_OK) rc = kgs::sim_close(s, s->stream);  // the step's own last sweep
     if (rc != KGS_OK) return rc;
     hipError_t e = hipStreamSynchronize(s->stream);
     return e == hipSuccess ? KGS_OK : hip_fail(s, e, "hipStreamSynchronize");

@@ -121,6 +121,20 @@ def test_autotune_on_an_open_state_keeps_it():
     assert same(got, straight(p, 7))
 
 
+def test_sync_completes_the_steps():
+    # kgs_sync applies the pending closing sweep: a run of calls with syncs
+    # in between ends where one uninterrupted run does
+    p = workloads.random_problem(3, 96, seed=10, tau=0.02, amp=0.5)
+    say("sync between calls")
+    s = kgs.simulation_from_problem(p)
+    for k in (3, 2, 4):
+        s.step(k)
+        s.sync()
+    got = s.read_state()
+    s.close()
+    assert same(got, straight(p, 9))
+
+
 def test_repeated_calls_as_in_the_bench():
     # the bench times repeated calls of K steps followed by one energy
     p = workloads.random_problem(3, 96, seed=9, tau=0.02, amp=0.5)
