@@ -152,7 +152,7 @@ bool apply_group(kgs_batch *b, BatchClass &c, const kgs::GroupTuning &t)
             tb += kgs::stream2d_tasks(n, t.chunk);
         }
     }
-    if (tb > 0x7fffffff) return false;
+    if (tb > 0x7ffffff0) return false;  // the launch's item limit
     c.s3 = t.mode == kgs::GROUP_STREAM3D;
     c.s2 = !c.s3;
     c.s2_tile = t.mode == kgs::GROUP_TILE2D;
@@ -517,7 +517,7 @@ int kgs_batch_create(kgs_sim *const *sims, int32_t count, void *stream, kgs_batc
                 std::vector<int> sizes(nm);
                 for (size_t i = 0; i < nm; ++i) sizes[i] = b->sims[c.members[i]]->geo.n;
                 const int chunk = kgs::stream3d_list_chunk(sizes.data(), static_cast<int>(nm), eb);
-                bool ok = items(chunk) <= 0x7fffffff;
+                bool ok = items(chunk) <= 0x7ffffff0;  // the launch's item limit
                 for (size_t i = 0; i < nm && ok; ++i) {
                     const kgs_sim *x = b->sims[c.members[i]];
                     ok = x->geo.n >= kStream3dMinN && kgs::stream3d_list_ok(x->geo, chunk, eb);

@@ -13,9 +13,9 @@
 namespace kgs {
 
 // A launch's workgroups are dealt to the 8 XCDs in turn, and xcd_item
-// gives XCD x the x-th eighth of the items in order (every item to XCD
-// item mod 8 when the count is not a multiple of 8); each XCD starts its
-// next item on the first of its CUs that is free.  An item of L planes
+// gives XCD x the x-th of 8 contiguous slices of ceil(items / 8) items (the
+// last slices shorter); each XCD starts its next item on the first of its
+// CUs that is free.  An item of L planes
 // takes L + kItemSteps pipeline steps: on MI355X at 256^3 float64 a launch
 // of one round of 128-plane items took 260 us, of two rounds of 64-plane
 // items 291 us (145.5 per item), which puts the fixed cost of an item
@@ -49,15 +49,13 @@ double stream3d_launch_steps(const int *n, int count, int tile_x, int tile_y, in
     }
     const int groups = cus % kXcds == 0 ? kXcds : 1;
     const int per = cus / groups;
-    const bool slices = groups == kXcds && items % kXcds == 0;
+    const int64_t q = (items + groups - 1) / groups;  // items per slice
     double end = 0.0;
     for (int x = 0; x < groups; ++x) {
         std::priority_queue<int64_t, std::vector<int64_t>, std::greater<int64_t>> free_at;
         for (int c = 0; c < per; ++c) free_at.push(0);
-        const int64_t first = groups == 1 ? 0 : slices ? x * (items / kXcds) : x;
-        const int64_t last = groups == 1 || !slices ? items : (x + 1) * (items / kXcds);
-        const int64_t step = groups == 1 || slices ? 1 : kXcds;
-        for (int64_t i = first; i < last; i += step) {
+        const int64_t first = x * q, last = std::min(items, (x + 1) * q);
+        for (int64_t i = first; i < last; ++i) {
             const int64_t t = free_at.top() + len[static_cast<size_t>(i)];
             free_at.pop();
             free_at.push(t);
