@@ -91,19 +91,22 @@ public:
     }
 
     // A free block of at least `bytes` and at most twice that, else a new
-    // one; NULL at the cap or when pinning fails.
+    // one; at the cap (or when pinning fails) the smallest free block that
+    // is large enough, else NULL.
     void *take(size_t bytes)
     {
         std::lock_guard<std::mutex> lk(mu_);
         auto it = free_.lower_bound(bytes);
-        if (it != free_.end() && it->first <= 2 * bytes) {
-            void *p = it->second;
+        auto reuse = [&] {
+            void *q = it->second;
             free_.erase(it);
-            return p;
-        }
-        if (total_ + bytes > cap()) return nullptr;
+            return q;
+        };
+        if (it != free_.end() && it->first <= 2 * bytes) return reuse();
         void *p = nullptr;
-        if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess || !p) return nullptr;
+        if (total_ + bytes > cap() ||
+            hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess || !p)
+            return it != free_.end() ? reuse() : nullptr;
         size_[p] = bytes;
         total_ += bytes;
         return p;
