@@ -179,3 +179,29 @@ def test_energy_that_closes_the_step_equals_sweep_then_energy(dim, n, prec):
     psi, u, v = sa
     ref = oracle.energy(oracle_check.grid_of(p), oracle.State.from_fields(psi, u, v))
     assert abs(ea - ref) <= 1e-13 * abs(ref)
+
+
+@pytest.mark.parametrize("dim,n", [(1, 8192), (2, 2), (2, 6), (3, 2), (3, 4), (3, 10)])
+@pytest.mark.parametrize("prec", [workloads.FP64, workloads.FP32])
+def test_closing_energy_on_small_and_1d_grids(dim, n, prec):
+    # one colour sweep per launch: n = 2 (each neighbour along an axis is
+    # the same point twice), odd chunkings of tiny planes, and 1-D grids,
+    # whose energy closes the step with the sweep kernel first
+    p = workloads.random_problem(dim, n, seed=80 + n + dim, tau=0.02, amp=0.5, precision=prec)
+    say("closing energy, sweeps", dim, n, prec)
+    a = kgs.simulation_from_problem(p, tuning=SWEEP)
+    b = kgs.simulation_from_problem(p, tuning=SWEEP)
+    a.step(3)
+    b.step(3)
+    ea = a.energy()
+    sa = a.read_state()
+    sb = b.read_state()
+    eb = b.energy()
+    a.close()
+    b.close()
+    assert same(sa, sb)
+    assert ea == eb
+    oracle_check.check(p, sa, 3, label=f"closing energy (sweeps) {dim}-D n={n}", cache=True)
+    psi, u, v = sa
+    ref = oracle.energy(oracle_check.grid_of(p), oracle.State.from_fields(psi, u, v))
+    assert abs(ea - ref) <= 1e-13 * abs(ref)
