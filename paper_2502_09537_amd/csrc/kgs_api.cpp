@@ -219,8 +219,9 @@ kgs_tuning default_tuning(const kgs_config &c, bool with_chunk = true)
         while (t.chunk > 8 && kgs::stream2d_tasks(c.n, t.chunk) < 8192) t.chunk /= 2;
     } else if (c.dim == 3 && c.n >= 96) {
         t.kernel = KGS_KERNEL_STREAM;
-        if (c.precision == KGS_FP32 && c.n >= 128) t.tile_y = 32;
-        if (with_chunk) t.chunk = kgs::stream3d_chunk(&c.n, 1, t.tile_x, t.tile_y, kgs::device_cus());
+        if (with_chunk)
+            kgs::stream3d_plan(c.n, static_cast<int>(elem_bytes(c.precision)), kgs::device_cus(),
+                               &t.tile_x, &t.tile_y, &t.chunk);
     }
     return t;
 }

@@ -80,6 +80,35 @@ int stream3d_chunk(const int *n, int count, int tile_x, int tile_y, int cus)
     return best;
 }
 
+// The float64 pipeline holds 162 VGPRs per thread at run-time tile shapes,
+// so 12 waves per CU (3 per SIMD) fit.  32x13 is the 12-wave tile whose
+// rows are a power of two wide (compressed positions: whole tiles along x
+// at power-of-two n); its halo rings add 0.82 of the tile's columns
+// against 0.88 for 16x16.  Measured on MI355X, float64, us per 2-step
+// launch, 16x16 against 32x13 (each with its planned chunk): 256^3 236.7
+// against 238-240, 320^3 620 / 611, 352^3 787 / 751, 384^3 943 / 845,
+// 448^3 1547 / 1504, 512^3 2020 / 1905, 640^3 4759-4936 / 4093-4372.
+// Divided by the estimated plane-steps, a 32x13 plane-step took 1.38-1.53
+// times a 16x16 one.
+void stream3d_plan(int n, int elem_bytes, int cus, int *tile_x, int *tile_y, int *chunk)
+{
+    if (elem_bytes != 8) {
+        *tile_x = 16;
+        *tile_y = n >= 128 ? 32 : 16;
+        *chunk = stream3d_chunk(&n, 1, *tile_x, *tile_y, cus);
+        return;
+    }
+    constexpr double kWideCost = 1.45, kMargin = 0.98;
+    const int c16 = stream3d_chunk(&n, 1, 16, 16, cus);
+    const int cw = stream3d_chunk(&n, 1, 32, 13, cus);
+    const double t16 = stream3d_launch_steps(&n, 1, 16, 16, c16, cus);
+    const double tw = kWideCost * stream3d_launch_steps(&n, 1, 32, 13, cw, cus);
+    const bool wide = tw < kMargin * t16;
+    *tile_x = wide ? 32 : 16;
+    *tile_y = wide ? 13 : 16;
+    *chunk = wide ? cw : c16;
+}
+
 bool energy_grid(int dim, int n, int cus, int64_t *bx, int64_t *by, int64_t *chunk)
 {
     constexpr int kBlock = 256, kSlots = 2048, kResident = 3, kStartSteps = 2;

@@ -20,6 +20,13 @@ double stream3d_launch_steps(const int *n, int count, int tile_x, int tile_y, in
 int stream3d_chunk(const int *n, int count, int tile_x, int tile_y, int cus);
 int stream3d_list_chunk(const int *n, int count, int elem_bytes);
 
+// Tile and plane chunk of a four-sweep z-streaming launch over one n^3 grid
+// with state elements of elem_bytes.  float32: 16x32 tiles from n = 128,
+// else 16x16.  float64: 32x13 (12 waves) when its launch is estimated to
+// end at least 2% before that of 16x16 (8 waves), the plane-steps of a
+// 32x13 workgroup counted 1.45 times those of a 16x16 one; else 16x16.
+void stream3d_plan(int n, int elem_bytes, int cus, int *tile_x, int *tile_y, int *chunk);
+
 // Grid of the streaming energy reduction of a 2-D or 3-D grid (workgroups
 // of 256 columns of a plane of axis 0, bx per plane, by chunks of `chunk`
 // planes): the closing form holds three workgroups per CU, so the chunk is

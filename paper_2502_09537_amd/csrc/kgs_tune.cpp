@@ -133,6 +133,7 @@ std::vector<kgs_tuning> candidates(const kgs_sim *s)
             {16, 32, 64, 1},  {32, 8, 32, 1},   {16, 16, 32, 2}, {32, 20, 64, 2},
             {16, 16, 16, 2},  {16, 16, 8, 2},   {16, 16, 16, 1},  {16, 32, 128, 2},
             {16, 32, 64, 2},  {16, 32, 32, 2},  {16, 32, 16, 2},  {16, 32, 8, 2},
+            {32, 13, 128, 2}, {32, 13, 96, 2},  {32, 13, 64, 2},  {32, 13, 48, 2},
         };
         for (const auto &sh : shapes) {
             kgs::StreamShape ss = {sh[0], sh[1], sh[2], sh[3]};

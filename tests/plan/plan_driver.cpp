@@ -1,7 +1,8 @@
 // Prints the launch estimate and the chosen chunk of the z-streaming launch
 // planner for one group of grids: plan_driver tile_x tile_y cus chunk n...
 // (chunk 0: only the chosen chunk); or the energy reduction's grid:
-// plan_driver energy dim n cus.  The planner's two device-facing
+// plan_driver energy dim n cus; or a single grid's tile and chunk:
+// plan_driver plan n elem_bytes cus.  The planner's two device-facing
 // helpers are stood in for here: no GPU is needed.
 #include <cstdio>
 #include <cstdlib>
@@ -28,6 +29,14 @@ int main(int argc, char **argv)
                                          std::atoi(argv[4]), &bx, &by, &chunk);
         std::printf("%lld %lld %lld\n", static_cast<long long>(ok ? bx : 0),
                     static_cast<long long>(ok ? by : 0), static_cast<long long>(ok ? chunk : 0));
+        return 0;
+    }
+    if (argc == 5 && std::string(argv[1]) == "plan") {
+        // plan_driver plan n elem_bytes cus: tile_x tile_y chunk
+        int tx = 0, ty = 0, chunk = 0;
+        kgs::stream3d_plan(std::atoi(argv[2]), std::atoi(argv[3]), std::atoi(argv[4]), &tx, &ty,
+                           &chunk);
+        std::printf("%d %d %d\n", tx, ty, chunk);
         return 0;
     }
     if (argc < 6) return 2;

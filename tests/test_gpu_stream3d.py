@@ -56,6 +56,8 @@ SHAPES = [
     (36, 4, 16, 16, 128, 2),  # chunk longer than the grid
     (58, 3, 16, 28, 20, 2),   # 720 threads (3 waves per SIMD), ragged
     (30, 2, 20, 20, 9, 2),    # a 768-thread runtime shape
+    (70, 3, 32, 13, 20, 2),   # the wide float64 tile (756 threads), ragged along x, y and z
+    (66, 2, 32, 13, 30, 2),   # the same, tiles wider than the grid's 33 positions
 ]
 
 
@@ -139,6 +141,38 @@ def test_default_chunk_on_a_grid_between_whole_rounds(prec):
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
     assert ea == eb
+
+
+def test_default_fp64_wide_tile_at_full_size_equals_sweep():
+    """At 384^3 the float64 default is the 12-wave 32x13 tile with 96-plane
+    chunks (180 tiles x 4 chunks); two steps give bitwise the state of the
+    colour sweeps.  At 256^3 the default stays 16x16 x 128 planes."""
+    import torch
+
+    say("float64 default tile 256^3 / 384^3")
+    for n, want in ((256, (16, 16, 128)), (384, (32, 13, 96))):
+        cfg = kgs.make_config(3, n, -8.0, 8.0, 0.002)
+        f = workloads.random_fields_torch(3, n, seed=29)
+        psi = torch.complex(f[0], f[1])
+        states = []
+        for t in (None, sweep_tuning()):
+            sim = kgs.Simulation(cfg, psi, f[2], f[3], tuning=t)
+            try:
+                if t is None:
+                    d = sim.tuning
+                    assert d.kernel == kgs.KGS_KERNEL_STREAM
+                    assert (d.tile_x, d.tile_y, d.chunk) == want
+                    if n == 256:
+                        break
+                sim.step(2)
+                states.append(sim.read_state(as_torch=True))
+            finally:
+                sim.close()
+        if n == 384:
+            for x, y in zip(*states):
+                assert torch.equal(x, y)
+        del f, psi, states
+        torch.cuda.empty_cache()
 
 
 def test_stream_matches_oracle_3d_config_reduced():

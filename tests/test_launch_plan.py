@@ -41,7 +41,12 @@ def driver(tmp_path_factory):
         out = subprocess.run([exe, "energy", str(dim), str(n), str(cus)], check=True,
                              capture_output=True, text=True, timeout=60).stdout.split()
         return tuple(int(v) for v in out)
+    def plan(n, elem_bytes, cus):
+        out = subprocess.run([exe, "plan", str(n), str(elem_bytes), str(cus)], check=True,
+                             capture_output=True, text=True, timeout=60).stdout.split()
+        return tuple(int(v) for v in out)
     run.energy = energy
+    run.plan = plan
     return run
 
 
@@ -114,6 +119,32 @@ def test_chosen_chunk_is_the_fastest_estimate(driver):
     # list launches: the precision's tile (16x16 float64, 16x32 float32)
     _, _, l64, l32 = driver(16, 16, 256, 0, sizes)
     assert l64 == best and l32 == driver(16, 32, 256, 0, sizes)[0]
+
+
+# A single grid's tile: float64 takes 32x13 (12 waves) when its launch is
+# estimated to end at least 2% before that of 16x16, counting a 32x13
+# plane-step as 1.45 16x16 ones.  Measured on MI355X (us per 2-step launch,
+# 16x16 against 32x13): 256^3 236.7 / 238-240, 320^3 620 / 611, 352^3
+# 787 / 751, 384^3 943 / 845, 448^3 1547 / 1504, 512^3 2020 / 1905, 640^3
+# 4759-4936 / 4093-4372.
+@pytest.mark.parametrize("n,eb,want", [
+    (256, 8, (16, 16, 128)), (224, 8, (16, 16, 48)), (320, 8, (16, 16, 64)), (96, 8, (16, 16, 8)),
+    (352, 8, (32, 13, 128)), (384, 8, (32, 13, 96)), (448, 8, (32, 13, 96)),
+    (512, 8, (32, 13, 128)), (640, 8, (32, 13, 128)), (1024, 8, (32, 13, 128)),
+    (256, 4, (16, 32, 64)), (512, 4, (16, 32, 128)), (96, 4, (16, 16, 8)),
+])
+def test_single_grid_tiles(driver, n, eb, want):
+    assert driver.plan(n, eb, 256) == want
+
+
+@pytest.mark.parametrize("cus", [256, 80])
+def test_single_grid_tile_rule(driver, cus):
+    for n in range(96, 1025, 32):
+        c16 = driver(16, 16, cus, 0, [n])[0]
+        cw = driver(32, 13, cus, 0, [n])[0]
+        t16, tw = simulate(16, 16, cus, c16, [n]), simulate(32, 13, cus, cw, [n])
+        want = (32, 13, cw) if 1.45 * tw < 0.98 * t16 else (16, 16, c16)
+        assert driver.plan(n, 8, cus) == want, n
 
 
 # The energy reduction's grid: workgroups of 256 columns of a plane of axis
