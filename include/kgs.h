@@ -262,8 +262,9 @@ int64_t kgs_required_bytes(const kgs_config *cfg);
  * class over all members instead of one launch per simulation: members that
  * fit one workgroup run a whole call in one persistent launch; 2-D members
  * run 2 steps per launch (y-streaming or tiled kernel) and 3-D members of
- * n >= 32 run 2 steps per launch of the z-streaming kernel (16x16 tiles in
- * float64, 16x32 in float32), in uniform runs of 2 or more steps; every
+ * n >= 32 run 2 steps per launch of the z-streaming kernel (float32: 16x32
+ * tiles; float64: 16x16, or 32x13 where the launch planner expects the
+ * class to end sooner with it), in uniform runs of 2 or more steps; every
  * other run is one launch per colour sweep.  A uniform run can be captured
  * once in a hipGraph and replayed.
  * Every member ends bitwise where kgs_step would have left it (points of one
@@ -296,7 +297,8 @@ int kgs_batch_free(kgs_batch *b);
 
 /* Time the launch configurations of each streaming group of the batch (the
  * 2-D members: y-streaming chunks of 8..64 rows and tiles of 8x8 .. 32x32
- * points of one colour; the 3-D members: plane chunks of 8..128) over
+ * points of one colour; the 3-D members: plane chunks of 8..128, in
+ * float64 with 16x16 and 32x13 tiles) over
  * uniform runs of `steps` steps (>= 2; a warm-up, then the faster of two
  * timed runs, each from the members' states, which are restored), and keep
  * the fastest for each group.  Every configuration gives bitwise the same

@@ -48,7 +48,8 @@ struct BatchClass {
     bool s2_tile = false;
     // 3-D streaming (uniform runs of 3-D sweep classes whose members are all
     // n >= kStream3dMinN): the same descriptor triple, s2_tasks workgroups
-    // of the z-streaming kernel's member-list launch, chunk s2_chunk
+    // of the z-streaming kernel's member-list launch, chunk s2_chunk, tile
+    // s2_tx compressed positions x s2_ty rows
     bool s3 = false;
     int s2_ty = 0, s2_tx = 0;
 };
@@ -89,8 +90,8 @@ int bhip(kgs_batch *b, hipError_t e, const char *what)
 thread_local std::string g_batch_err;
 
 // 3-D members stream together when every member has n >= kStream3dMinN
-// (at least one full tile along x); the plane chunk of such a launch is the
-// one stream3d_list_chunk estimates to end it first.
+// (at least one full tile along x); the tile and plane chunk of such a
+// launch are those stream3d_list_plan estimates to end it first.
 constexpr int kStream3dMinN = 32;
 
 // Releases everything the batch holds; the first runtime error, if any.
@@ -137,13 +138,18 @@ bool apply_group(kgs_batch *b, BatchClass &c, const kgs::GroupTuning &t)
     const size_t nm = c.members.size();
     const int eb = c.precision == KGS_FP64 ? 8 : 4;
     if ((t.mode == kgs::GROUP_STREAM3D) != (c.dim == 3) || t.chunk < 1) return false;
+    // 3-D: a tile of 0 x 0 is the precision's default list tile
+    int tx3 = t.tx, ty3 = t.ty;
+    if (t.mode == kgs::GROUP_STREAM3D && (tx3 < 1 || ty3 < 1))
+        kgs::stream3d_list_tile(eb, &tx3, &ty3);
     int64_t tb = 0;
     for (size_t i = 0; i < nm; ++i) {
         const kgs_sim *x = b->sims[c.members[i]];
         const int n = x->geo.n;
         if (t.mode == kgs::GROUP_STREAM3D) {
-            if (n < kStream3dMinN || !kgs::stream3d_list_ok(x->geo, t.chunk, eb)) return false;
-            tb += kgs::stream3d_member_items(n, t.chunk, eb);
+            if (n < kStream3dMinN || !kgs::stream3d_list_ok(x->geo, t.chunk, eb, tx3, ty3))
+                return false;
+            tb += kgs::stream3d_member_items(n, t.chunk, tx3, ty3);
         } else if (t.mode == kgs::GROUP_TILE2D) {
             if (!kgs::tile2d_shape_ok(x->geo, t.ty, t.tx, 4, eb)) return false;
             tb += kgs::tile2d_member_tiles(n, t.ty, t.tx);
@@ -157,8 +163,8 @@ bool apply_group(kgs_batch *b, BatchClass &c, const kgs::GroupTuning &t)
     c.s2 = !c.s3;
     c.s2_tile = t.mode == kgs::GROUP_TILE2D;
     c.s2_chunk = t.chunk;
-    c.s2_ty = t.ty;
-    c.s2_tx = t.tx;
+    c.s2_ty = c.s3 ? ty3 : t.ty;
+    c.s2_tx = c.s3 ? tx3 : t.tx;
     tb = 0;
     for (size_t i = 0; i < nm; ++i) {
         const kgs_sim *x = b->sims[c.members[i]];
@@ -175,7 +181,7 @@ bool apply_group(kgs_batch *b, BatchClass &c, const kgs::GroupTuning &t)
                                              : kgs::stream2d_tiles_x(n);
             // in/out/first are set by refresh_descriptors
         }
-        tb += c.s3 ? kgs::stream3d_member_items(n, c.s2_chunk, c.precision == KGS_FP64 ? 8 : 4)
+        tb += c.s3 ? kgs::stream3d_member_items(n, c.s2_chunk, c.s2_tx, c.s2_ty)
                    : c.s2_tile ? kgs::tile2d_member_tiles(n, c.s2_ty, c.s2_tx)
                                : kgs::stream2d_tasks(n, c.s2_chunk);
     }
@@ -252,8 +258,8 @@ hipError_t enqueue_stream_class(kgs_batch *b, const BatchClass &c, int64_t nstep
         const kgs::Stream2dMember *list = c.d_s2 + (i == 0 ? 0 : (i % 2 ? 2 * nm : nm));
         hipError_t e;
         if (c.s3)
-            e = kgs::launch_stream3d_list(c.precision, stages[i], list, nm, c.s2_tasks, i == 0,
-                                          b->own);
+            e = kgs::launch_stream3d_list(c.precision, stages[i], c.s2_tx, c.s2_ty, list, nm,
+                                          c.s2_tasks, i == 0, b->own);
         else if (c.s2_tile)
             e = kgs::launch_tile2d_list(c.precision, stages[i], c.s2_ty, c.s2_tx, none, list, nm,
                                         c.s2_tasks, b->own, i == 0 ? 1 : 0);
@@ -504,23 +510,21 @@ int kgs_batch_create(kgs_sim *const *sims, int32_t count, void *stream, kgs_batc
             } else if (c.dim == 3) {
                 // 3-D runs of several steps: the z-streaming kernel over all
                 // members in one launch when every member is large enough
-                // for its tile (else batched sweeps), with the plane chunk
-                // (8..128) estimated to end the launch first
+                // for its tile (else batched sweeps), with the tile and plane
+                // chunk (8..128) estimated to end the launch first
                 const size_t nm = c.members.size();
                 const int eb = c.precision == KGS_FP64 ? 8 : 4;
-                auto items = [&](int ch) {
-                    int64_t t = 0;
-                    for (size_t i = 0; i < nm; ++i)
-                        t += kgs::stream3d_member_items(b->sims[c.members[i]]->geo.n, ch, eb);
-                    return t;
-                };
                 std::vector<int> sizes(nm);
                 for (size_t i = 0; i < nm; ++i) sizes[i] = b->sims[c.members[i]]->geo.n;
-                const int chunk = kgs::stream3d_list_chunk(sizes.data(), static_cast<int>(nm), eb);
-                bool ok = items(chunk) <= 0x7ffffff0;  // the launch's item limit
+                int tx = 0, ty = 0, chunk = 0;
+                kgs::stream3d_list_plan(sizes.data(), static_cast<int>(nm), eb, &tx, &ty, &chunk);
+                int64_t items = 0;
+                for (size_t i = 0; i < nm; ++i) items += kgs::stream3d_member_items(sizes[i], chunk, tx, ty);
+                bool ok = items <= 0x7ffffff0;  // the launch's item limit
                 for (size_t i = 0; i < nm && ok; ++i) {
                     const kgs_sim *x = b->sims[c.members[i]];
-                    ok = x->geo.n >= kStream3dMinN && kgs::stream3d_list_ok(x->geo, chunk, eb);
+                    ok = x->geo.n >= kStream3dMinN &&
+                         kgs::stream3d_list_ok(x->geo, chunk, eb, tx, ty);
                 }
                 if (!ok) continue;
                 for (size_t i = 0; i < nm && code == KGS_OK; ++i)
@@ -531,6 +535,8 @@ int kgs_batch_create(kgs_sim *const *sims, int32_t count, void *stream, kgs_batc
                 }
                 c.s3 = true;
                 c.s2_chunk = chunk;
+                c.s2_tx = tx;
+                c.s2_ty = ty;
                 const size_t s3bytes = 3 * nm * sizeof(kgs::Stream2dMember);
                 if ((e = hipMalloc(reinterpret_cast<void **>(&c.d_s2), s3bytes)) != hipSuccess ||
                     (e = hipHostMalloc(reinterpret_cast<void **>(&c.h_s2), s3bytes,
@@ -768,7 +774,11 @@ int kgs_batch_autotune(kgs_batch *b, int32_t steps, int32_t use_cache)
         e = copy_states(true);
         std::vector<kgs::GroupTuning> cands{group_of(c)};  // the default first
         if (c.dim == 3) {
-            for (int ch : {8, 16, 32, 64, 128}) cands.push_back({kgs::GROUP_STREAM3D, ch, 0, 0});
+            // float64 also tries the 12-wave 32x13 tile (GroupTuning: ty, tx)
+            for (int ch : {8, 16, 32, 64, 128}) {
+                cands.push_back({kgs::GROUP_STREAM3D, ch, 0, 0});
+                if (c.precision == KGS_FP64) cands.push_back({kgs::GROUP_STREAM3D, ch, 13, 32});
+            }
         } else {
             for (int ch : {8, 16, 32, 64}) cands.push_back({kgs::GROUP_STREAM2D, ch, 0, 0});
             const int tiles[][2] = {{8, 8}, {8, 16}, {16, 16}, {16, 32}, {32, 32}};

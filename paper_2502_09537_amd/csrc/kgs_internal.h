@@ -149,19 +149,21 @@ hipError_t launch_sweep(const Geometry &g, int precision, void *state, int kind,
 bool stream3d_shape_ok(const Geometry &g, const StreamShape &sh, int elem_bytes);
 hipError_t launch_stream3d(const Geometry &g, int precision, const StreamShape &sh, int stages,
                            const void *in, void *out, bool first, const Coef &k, hipStream_t s);
-// 3-D streaming over several grids of one precision in one launch, with the
-// tile stream3d_list_tile() gives for that precision (element bytes 8 or
+// 3-D streaming over several grids of one precision in one launch, all
+// with the tile tile_x x tile_y (compressed positions x rows;
+// stream3d_list_tile() gives the precision's default, element bytes 8 or
 // 4): member m (sorted by task_begin, the first workgroup it owns) takes
-// stream3d_member_items(n, chunk, elem_bytes) workgroups and advances
+// stream3d_member_items(n, chunk, tile_x, tile_y) workgroups and advances
 // `stages` (2 or 4) sweeps from in to out (the Stream2dMember fields
 // tiles_x and first are not read: the launch's first sweep is R_BASE when
 // `first`).  stream3d_list_ok: whether a grid fits a list launch with that
-// chunk (checked by the caller for every member).
+// chunk and tile (checked by the caller for every member).
 void stream3d_list_tile(int elem_bytes, int *tile_x, int *tile_y);
-int64_t stream3d_member_items(int n, int chunk, int elem_bytes);
-bool stream3d_list_ok(const Geometry &g, int chunk, int elem_bytes);
-hipError_t launch_stream3d_list(int precision, int stages, const Stream2dMember *list, int nm,
-                                int64_t total_items, bool first, hipStream_t s);
+int64_t stream3d_member_items(int n, int chunk, int tile_x, int tile_y);
+bool stream3d_list_ok(const Geometry &g, int chunk, int elem_bytes, int tile_x, int tile_y);
+hipError_t launch_stream3d_list(int precision, int stages, int tile_x, int tile_y,
+                                const Stream2dMember *list, int nm, int64_t total_items,
+                                bool first, hipStream_t s);
 // Batched sweep over `nm` members (sorted by block_begin, blocks of
 // batch_block() threads).  Kinds: kinds[launch * nm + i] (-1 = idle) if
 // kinds != NULL, else uniform_kind for every member.

@@ -90,23 +90,32 @@ int stream3d_chunk(const int *n, int count, int tile_x, int tile_y, int cus)
 // 448^3 1547 / 1504, 512^3 2020 / 1905, 640^3 4759-4936 / 4093-4372.
 // Divided by the estimated plane-steps, a 32x13 plane-step took 1.38-1.53
 // times a 16x16 one.
-void stream3d_plan(int n, int elem_bytes, int cus, int *tile_x, int *tile_y, int *chunk)
+namespace {
+
+void plan_fp64(const int *n, int count, int cus, int *tile_x, int *tile_y, int *chunk)
 {
-    if (elem_bytes != 8) {
-        *tile_x = 16;
-        *tile_y = n >= 128 ? 32 : 16;
-        *chunk = stream3d_chunk(&n, 1, *tile_x, *tile_y, cus);
-        return;
-    }
     constexpr double kWideCost = 1.45, kMargin = 0.98;
-    const int c16 = stream3d_chunk(&n, 1, 16, 16, cus);
-    const int cw = stream3d_chunk(&n, 1, 32, 13, cus);
-    const double t16 = stream3d_launch_steps(&n, 1, 16, 16, c16, cus);
-    const double tw = kWideCost * stream3d_launch_steps(&n, 1, 32, 13, cw, cus);
+    const int c16 = stream3d_chunk(n, count, 16, 16, cus);
+    const int cw = stream3d_chunk(n, count, 32, 13, cus);
+    const double t16 = stream3d_launch_steps(n, count, 16, 16, c16, cus);
+    const double tw = kWideCost * stream3d_launch_steps(n, count, 32, 13, cw, cus);
     const bool wide = tw < kMargin * t16;
     *tile_x = wide ? 32 : 16;
     *tile_y = wide ? 13 : 16;
     *chunk = wide ? cw : c16;
+}
+
+}  // namespace
+
+void stream3d_plan(int n, int elem_bytes, int cus, int *tile_x, int *tile_y, int *chunk)
+{
+    if (elem_bytes == 8) {
+        plan_fp64(&n, 1, cus, tile_x, tile_y, chunk);
+        return;
+    }
+    *tile_x = 16;
+    *tile_y = n >= 128 ? 32 : 16;
+    *chunk = stream3d_chunk(&n, 1, *tile_x, *tile_y, cus);
 }
 
 bool energy_grid(int dim, int n, int cus, int64_t *bx, int64_t *by, int64_t *chunk)
@@ -132,11 +141,16 @@ bool energy_grid(int dim, int n, int cus, int64_t *bx, int64_t *by, int64_t *chu
     return best >= 0.0;
 }
 
-int stream3d_list_chunk(const int *n, int count, int elem_bytes)
+void stream3d_list_plan(const int *n, int count, int elem_bytes, int *tile_x, int *tile_y,
+                        int *chunk)
 {
-    int tx = 0, ty = 0;
-    stream3d_list_tile(elem_bytes, &tx, &ty);
-    return stream3d_chunk(n, count, tx, ty, device_cus());
+    const int cus = device_cus();
+    if (elem_bytes == 8) {
+        plan_fp64(n, count, cus, tile_x, tile_y, chunk);
+        return;
+    }
+    stream3d_list_tile(elem_bytes, tile_x, tile_y);
+    *chunk = stream3d_chunk(n, count, *tile_x, *tile_y, cus);
 }
 
 }  // namespace kgs

@@ -15,10 +15,8 @@ int device_cus();
 double stream3d_launch_steps(const int *n, int count, int tile_x, int tile_y, int chunk, int cus);
 
 // The plane chunk (8..128) whose launch is estimated to end first, the
-// longer of two within 1%.  stream3d_list_chunk: the same for a
-// member-list launch of that precision on the current device.
+// longer of two within 1%.
 int stream3d_chunk(const int *n, int count, int tile_x, int tile_y, int cus);
-int stream3d_list_chunk(const int *n, int count, int elem_bytes);
 
 // Tile and plane chunk of a four-sweep z-streaming launch over one n^3 grid
 // with state elements of elem_bytes.  float32: 16x32 tiles from n = 128,
@@ -26,6 +24,12 @@ int stream3d_list_chunk(const int *n, int count, int elem_bytes);
 // end at least 2% before that of 16x16 (8 waves), the plane-steps of a
 // 32x13 workgroup counted 1.45 times those of a 16x16 one; else 16x16.
 void stream3d_plan(int n, int elem_bytes, int cus, int *tile_x, int *tile_y, int *chunk);
+
+// The same for a member-list launch over grids n[0..count) of one
+// precision on the current device: float32 takes its default list tile
+// (stream3d_list_tile), float64 the rule above over the whole list.
+void stream3d_list_plan(const int *n, int count, int elem_bytes, int *tile_x, int *tile_y,
+                        int *chunk);
 
 // Grid of the streaming energy reduction of a 2-D or 3-D grid (workgroups
 // of 256 columns of a plane of axis 0, bx per plane, by chunks of `chunk`

@@ -855,18 +855,34 @@ int run_stream2d(kgs_server *s, int prec, int64_t k, const std::vector<Request *
     return KGS_OK;
 }
 
+// Whether a 3-D grid fits a member-list launch with the default tile of
+// its precision (chunk 8, the shortest the planner takes).
+bool list_fits(const kgs::Geometry &g, int elem_bytes)
+{
+    int tx = 0, ty = 0;
+    kgs::stream3d_list_tile(elem_bytes, &tx, &ty);
+    return kgs::stream3d_list_ok(g, 8, elem_bytes, tx, ty);
+}
+
 // 3-D requests of one precision taking k >= 2 steps this round: the same
 // launch sequence as run_stream2d with the z-streaming kernel's member-list
-// launch over all of them (the list tile of the precision, the plane chunk
-// estimated to end the launch first), then the closing red sweep as one
-// batched sweep.
+// launch over all of them (the tile and plane chunk estimated to end the
+// launch first), then the closing red sweep as one batched sweep.
 int run_stream3d(kgs_server *s, int prec, int64_t k, const std::vector<Request *> &rs)
 {
     const int nm = static_cast<int>(rs.size());
     const int eb = prec == KGS_FP64 ? 8 : 4;
     std::vector<int> sizes;
     for (const Request *r : rs) sizes.push_back(r->sim->geo.n);
-    const int chunk = kgs::stream3d_list_chunk(sizes.data(), nm, eb);
+    int tx = 0, ty = 0, chunk = 0;
+    kgs::stream3d_list_plan(sizes.data(), nm, eb, &tx, &ty, &chunk);
+    for (const Request *r : rs)
+        if (!kgs::stream3d_list_ok(r->sim->geo, chunk, eb, tx, ty)) {
+            // every request was admitted for the default tile
+            kgs::stream3d_list_tile(eb, &tx, &ty);
+            chunk = kgs::stream3d_chunk(sizes.data(), nm, tx, ty, kgs::device_cus());
+            break;
+        }
     const size_t s3_bytes = align_up(3 * nm * sizeof(kgs::Stream2dMember), 256);
     const size_t bm_bytes = align_up(nm * sizeof(kgs::BatchMember), 256);
     int rc = KGS_OK;
@@ -890,7 +906,7 @@ int run_stream3d(kgs_server *s, int prec, int64_t k, const std::vector<Request *
             m.chunk = chunk;
             m.first = v == 0 ? 1 : 0;
         }
-        tb += kgs::stream3d_member_items(x->geo.n, chunk, eb);
+        tb += kgs::stream3d_member_items(x->geo.n, chunk, tx, ty);
         std::memset(&bm[i], 0, sizeof(bm[i]));
         bm[i].state = x->state;
         bm[i].stride = x->geo.stride;
@@ -908,7 +924,7 @@ int run_stream3d(kgs_server *s, int prec, int64_t k, const std::vector<Request *
     const auto *dd = reinterpret_cast<const kgs::Stream2dMember *>(sl->d);
     for (size_t i = 0; i < stages.size() && e == hipSuccess; ++i) {
         const kgs::Stream2dMember *list = dd + (i == 0 ? 0 : (i % 2 ? 2 * nm : nm));
-        e = kgs::launch_stream3d_list(prec, stages[i], list, nm, tb, i == 0, st);
+        e = kgs::launch_stream3d_list(prec, stages[i], tx, ty, list, nm, tb, i == 0, st);
     }
     if (e == hipSuccess && blocks > 0x7fffffff) e = hipErrorInvalidValue;
     if (e == hipSuccess)
@@ -962,7 +978,7 @@ int run_big(kgs_server *s)
             r->sim->err.clear();  // no second buffer: sweeps instead
         }
         if (r->cfg.dim == 3 && r->sim->tuning.kernel == KGS_KERNEL_STREAM && pk.second >= 2 &&
-            kgs::stream3d_list_ok(r->sim->geo, 8, r->cfg.precision == KGS_FP64 ? 8 : 4) &&
+            list_fits(r->sim->geo, r->cfg.precision == KGS_FP64 ? 8 : 4) &&
             r->sim->state2) {
             s3[{r->cfg.precision, pk.second}].push_back(r);
             continue;

@@ -468,13 +468,15 @@ hipError_t launch_typed(const Geometry &g, const StreamShape &sh, const T *in, T
     return hipGetLastError();
 }
 
-// Tile of the launches over member lists (compressed positions x rows),
-// the same for both sweep counts so that a member owns the same items in
-// every launch of a sequence.  float64: 16x16, compiled in (8 waves, the
-// LDS and registers of a workgroup per CU).  float32: 16x32 at run time
-// (13 waves at 128 VGPRs, half the LDS bytes): the halo rings add 0.64 of
-// the tile's columns instead of 0.88, and each SIMD holds 3-4 waves
-// (measured on MI355X at 256^3: 213 against 249 us per 2-step launch).
+// Default tile of the launches over member lists (compressed positions x
+// rows) per precision.  float64: 16x16, compiled in (8 waves, the LDS and
+// registers of a workgroup per CU).  float32: 16x32 at run time (13 waves
+// at 128 VGPRs, half the LDS bytes): the halo rings add 0.64 of the tile's
+// columns instead of 0.88, and each SIMD holds 3-4 waves (measured on
+// MI355X at 256^3: 213 against 249 us per 2-step launch).  A launch may
+// take another tile (float64 groups of large grids: 32x13, 12 waves); the
+// tile of a member's launches stays the same through a sequence, so that
+// the member owns the same items in every launch.
 struct ListTile {
     int x, y;
 };
@@ -482,23 +484,30 @@ struct ListTile {
 ListTile list_tile(int elem_bytes) { return elem_bytes == 8 ? ListTile{16, 16} : ListTile{16, 32}; }
 
 template <typename T, int S>
-hipError_t launch_list_typed(const Stream2dMember *list, int nm, int64_t items, bool first,
-                             hipStream_t s)
+hipError_t launch_list_typed(int tile_x, int tile_y, const Stream2dMember *list, int nm,
+                             int64_t items, bool first, hipStream_t s)
 {
-    const ListTile tl = list_tile(sizeof(T));
-    const int BX = tl.x + 2 * ((S + 1) / 2), BY = tl.y + 2 * S;
+    const int BX = tile_x + 2 * ((S + 1) / 2), BY = tile_y + 2 * S;
     const int threads = (BX * BY + 63) / 64 * 64;
     const size_t lds = static_cast<size_t>(2) * S * 3 * lds_plane(BX, BY) * sizeof(T);
-    constexpr bool fixed = sizeof(T) == 8;
-    constexpr int TX = fixed ? 16 : 0, TY = fixed ? 16 : 0;
-    if (threads > max_threads<T, S, TX, TY>() || lds > 160 * 1024) return hipErrorInvalidValue;
-    auto kern = first ? stream3d_list_kernel<T, S, true, TX, TY>
-                      : stream3d_list_kernel<T, S, false, TX, TY>;
+    // the float64 16x16 tile is compiled in, every other tile taken at run time
+    const bool fixed = sizeof(T) == 8 && tile_x == 16 && tile_y == 16;
+    auto kern = first ? stream3d_list_kernel<T, S, true, 0, 0>
+                      : stream3d_list_kernel<T, S, false, 0, 0>;
+    int limit = max_threads<T, S>();
+    if constexpr (sizeof(T) == 8) {
+        if (fixed) {
+            kern = first ? stream3d_list_kernel<T, S, true, 16, 16>
+                         : stream3d_list_kernel<T, S, false, 16, 16>;
+            limit = max_threads<T, S, 16, 16>();
+        }
+    }
+    if (tile_x < 1 || tile_y < 1 || threads > limit || lds > 160 * 1024)
+        return hipErrorInvalidValue;
     hipError_t e = allow_dynamic_lds(reinterpret_cast<const void *>(kern), static_cast<int>(lds));
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(xcd_grid(items))), dim3(threads), lds, s, list, nm,
-                       static_cast<int>(items),
-                       tl.x, tl.y);
+                       static_cast<int>(items), tile_x, tile_y);
     return hipGetLastError();
 }
 
@@ -511,31 +520,32 @@ void stream3d_list_tile(int elem_bytes, int *tile_x, int *tile_y)
     *tile_y = tl.y;
 }
 
-int64_t stream3d_member_items(int n, int chunk, int elem_bytes)
+int64_t stream3d_member_items(int n, int chunk, int tile_x, int tile_y)
 {
-    const ListTile tl = list_tile(elem_bytes);
-    const int64_t tx = (n / 2 + tl.x - 1) / tl.x, ty = (n + tl.y - 1) / tl.y;
+    const int64_t tx = (n / 2 + tile_x - 1) / tile_x, ty = (n + tile_y - 1) / tile_y;
     return tx * ty * ((n + chunk - 1) / chunk);
 }
 
-bool stream3d_list_ok(const Geometry &g, int chunk, int elem_bytes)
+bool stream3d_list_ok(const Geometry &g, int chunk, int elem_bytes, int tile_x, int tile_y)
 {
-    const ListTile tl = list_tile(elem_bytes);
-    const StreamShape sh = {tl.x, tl.y, chunk, 2};
+    const StreamShape sh = {tile_x, tile_y, chunk, 2};
     return stream3d_shape_ok(g, sh, elem_bytes);
 }
 
-hipError_t launch_stream3d_list(int precision, int stages, const Stream2dMember *list, int nm,
-                                int64_t total_items, bool first, hipStream_t s)
+hipError_t launch_stream3d_list(int precision, int stages, int tile_x, int tile_y,
+                                const Stream2dMember *list, int nm, int64_t total_items,
+                                bool first, hipStream_t s)
 {
     if (!list || nm < 1 || total_items < 1 || total_items > kMaxItems ||
         (stages != 2 && stages != 4))
         return hipErrorInvalidValue;
     if (precision == 0)
-        return stages == 2 ? launch_list_typed<double, 2>(list, nm, total_items, first, s)
-                           : launch_list_typed<double, 4>(list, nm, total_items, first, s);
-    return stages == 2 ? launch_list_typed<float, 2>(list, nm, total_items, first, s)
-                       : launch_list_typed<float, 4>(list, nm, total_items, first, s);
+        return stages == 2
+                   ? launch_list_typed<double, 2>(tile_x, tile_y, list, nm, total_items, first, s)
+                   : launch_list_typed<double, 4>(tile_x, tile_y, list, nm, total_items, first, s);
+    return stages == 2
+               ? launch_list_typed<float, 2>(tile_x, tile_y, list, nm, total_items, first, s)
+               : launch_list_typed<float, 4>(tile_x, tile_y, list, nm, total_items, first, s);
 }
 
 bool stream3d_shape_ok(const Geometry &g, const StreamShape &sh, int elem_bytes)

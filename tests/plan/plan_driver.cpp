@@ -47,7 +47,10 @@ int main(int argc, char **argv)
     const int count = static_cast<int>(n.size());
     const int best = kgs::stream3d_chunk(n.data(), count, tx, ty, cus);
     const double est = chunk > 0 ? kgs::stream3d_launch_steps(n.data(), count, tx, ty, chunk, cus) : 0.0;
-    std::printf("%d %.6f %d %d\n", best, est, kgs::stream3d_list_chunk(n.data(), count, 8),
-                kgs::stream3d_list_chunk(n.data(), count, 4));
+    int t64[3], t32[3];
+    kgs::stream3d_list_plan(n.data(), count, 8, &t64[0], &t64[1], &t64[2]);
+    kgs::stream3d_list_plan(n.data(), count, 4, &t32[0], &t32[1], &t32[2]);
+    std::printf("%d %.6f %d %d %d %d %d %d\n", best, est, t64[0], t64[1], t64[2], t32[0], t32[1],
+                t32[2]);
     return 0;
 }

@@ -274,6 +274,33 @@ def test_batch_3d_streaming_equals_individual_runs_and_oracle(graph, calls):
         assert same(again, ref2)
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_3d_wide_tile_group_equals_individual_runs_and_oracle(graph):
+    """A float64 group (n = 66, 98, 130, 162) whose member-list launches the
+    planner gives the 12-wave 32x13 tile (chunk 32): ragged tiles along x,
+    y and z in every member; run alone, each member streams with 16x16
+    tiles or sweeps."""
+    probs = [workloads.random_problem(3, n, seed=700 + n, tau=0.03, amp=0.5)
+             for n in (66, 98, 130, 162)]
+    say("3-D wide-tile batch, graph =", graph)
+    ref = []
+    for p in probs:
+        s = kgs.simulation_from_problem(p)
+        s.step(5)
+        ref.append(s.read_state())
+        s.close()
+    sims = [kgs.simulation_from_problem(p) for p in probs]
+    b = kgs.Batch(sims, graph=graph)
+    b.step(2)
+    b.step(3)
+    got = states(sims)
+    b.close()
+    for s in sims:
+        s.close()
+    assert same(got, ref)
+    match_oracle(probs, got, 5, f"3-D wide-tile batch (graph={graph})")
+
+
 def tuner_problems(seed=0):
     # a 2-D streaming group, a 3-D member-list group, a resident member and a
     # 3-D member below the list kernel's size (its class sweeps)

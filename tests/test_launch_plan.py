@@ -35,7 +35,8 @@ def driver(tmp_path_factory):
     def run(tx, ty, cus, chunk, sizes):
         out = subprocess.run([exe, str(tx), str(ty), str(cus), str(chunk), *map(str, sizes)],
                              check=True, capture_output=True, text=True, timeout=60).stdout.split()
-        return int(out[0]), float(out[1]), int(out[2]), int(out[3])
+        return (int(out[0]), float(out[1]), tuple(int(v) for v in out[2:5]),
+                tuple(int(v) for v in out[5:8]))
 
     def energy(dim, n, cus):
         out = subprocess.run([exe, "energy", str(dim), str(n), str(cus)], check=True,
@@ -116,9 +117,11 @@ def test_chosen_chunk_is_the_fastest_estimate(driver):
     best = driver(16, 16, 256, 0, sizes)[0]
     est = {c: simulate(16, 16, 256, c, sizes) for c in (128, 96, 64, 48, 32, 24, 16, 12, 8)}
     assert est[best] <= min(est.values()) / 0.99
-    # list launches: the precision's tile (16x16 float64, 16x32 float32)
+    # list launches: float32 with its list tile (16x32), float64 with the
+    # single-grid tile rule over the whole list
     _, _, l64, l32 = driver(16, 16, 256, 0, sizes)
-    assert l64 == best and l32 == driver(16, 32, 256, 0, sizes)[0]
+    assert l32 == (16, 32, driver(16, 32, 256, 0, sizes)[0])
+    assert l64 == fp64_rule(driver, 256, sizes)
 
 
 # A single grid's tile: float64 takes 32x13 (12 waves) when its launch is
@@ -137,14 +140,30 @@ def test_single_grid_tiles(driver, n, eb, want):
     assert driver.plan(n, eb, 256) == want
 
 
+def fp64_rule(driver, cus, sizes):
+    c16 = driver(16, 16, cus, 0, sizes)[0]
+    cw = driver(32, 13, cus, 0, sizes)[0]
+    t16, tw = simulate(16, 16, cus, c16, sizes), simulate(32, 13, cus, cw, sizes)
+    return (32, 13, cw) if 1.45 * tw < 0.98 * t16 else (16, 16, c16)
+
+
 @pytest.mark.parametrize("cus", [256, 80])
 def test_single_grid_tile_rule(driver, cus):
     for n in range(96, 1025, 32):
-        c16 = driver(16, 16, cus, 0, [n])[0]
-        cw = driver(32, 13, cus, 0, [n])[0]
-        t16, tw = simulate(16, 16, cus, c16, [n]), simulate(32, 13, cus, cw, [n])
-        want = (32, 13, cw) if 1.45 * tw < 0.98 * t16 else (16, 16, c16)
-        assert driver.plan(n, 8, cus) == want, n
+        assert driver.plan(n, 8, cus) == fp64_rule(driver, cus, [n]), n
+
+
+@pytest.mark.parametrize("sizes,want", [
+    ([256, 224, 192], (32, 13, 64)),             # three mid-size grids: 32x13
+    ([256] * 4, (16, 16, 128)),                  # whole rounds of 16x16 items
+    ([64] * 8, (16, 16, 16)),                    # small grids: ragged 32x13 tiles
+    ([224, 160, 160, 160, 256, 224, 96, 192, 256, 256, 128, 192, 192, 64, 192, 64],
+     (32, 13, 64)),                              # the 16-grid 3-D batch configuration
+])
+def test_list_tiles(driver, sizes, want):
+    _, _, l64, l32 = driver(16, 16, 256, 0, sizes)
+    assert l64 == want == fp64_rule(driver, 256, sizes)
+    assert l32[:2] == (16, 32)
 
 
 # The energy reduction's grid: workgroups of 256 columns of a plane of axis
