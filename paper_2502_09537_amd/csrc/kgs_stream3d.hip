@@ -452,10 +452,11 @@ hipError_t launch_typed(const Geometry &g, const StreamShape &sh, const T *in, T
     if (threads > max_threads<T, S>() || items > kMaxItems || lds > 160 * 1024)
         return hipErrorInvalidValue;
     // four-sweep launches of the 16x16 tile are compiled with the tile fixed
-    // (measured on MI355X at 256^3 float64: 16x16 beats taller tiles of up
-    // to 768 threads, e.g. 16x28).  Other shapes, among them the float32
-    // default 16x32, take it at run time: compiled in, 16x32 spills
-    // registers at the 128 VGPRs its 13 waves allow and lost 15%.
+    // (measured on MI355X at 256^3 float64: 16x16 beats tiles of up to 768
+    // threads, e.g. 16x28 and 32x13).  Other shapes take it at run time: the
+    // float32 default 16x32 (compiled in, it spills registers at the 128
+    // VGPRs its 13 waves allow and lost 15%) and the float64 32x13 of large
+    // grids (compiled in, no faster).
     auto kern = first ? stream3d_kernel<T, S, true, 0, 0> : stream3d_kernel<T, S, false, 0, 0>;
     if constexpr (S == 4) {
         if (sh.tile_x == 16 && sh.tile_y == 16)
