@@ -85,11 +85,13 @@ int stream3d_chunk(const int *n, int count, int tile_x, int tile_y, int cus)
 // rows are a power of two wide (compressed positions: whole tiles along x
 // at power-of-two n); its halo rings add 0.82 of the tile's columns
 // against 0.88 for 16x16.  Measured on MI355X, float64, us per 2-step
-// launch, 16x16 against 32x13 (each with its planned chunk): 256^3 236.7
-// against 238-240, 320^3 620 / 611, 352^3 787 / 751, 384^3 943 / 845,
-// 448^3 1547 / 1504, 512^3 2020 / 1905, 640^3 4759-4936 / 4093-4372.
-// Divided by the estimated plane-steps, a 32x13 plane-step took 1.38-1.53
-// times a 16x16 one.
+// launch, 16x16 against 32x13 (each with its planned chunk): 168^3 122 /
+// 100-104, 200^3 194 / 170-173, 256^3 236.7 / 238-240, 320^3 620 / 611,
+// 334^3 859-863 / 774-784, 352^3 787 / 751, 384^3 943 / 845, 448^3 1547 /
+// 1504, 512^3 2020 / 1905, 640^3 4759-4936 / 4093-4372, 734^3 7547-8884 /
+// 7518-7525.  Divided by the estimated plane-steps, a 32x13 plane-step
+// took 1.36-1.53 times a 16x16 one.  The rule keeps 16x16 at 256^3 and
+// misses only near-ties (320^3, 734^3: 32x13 faster by at most 1.5%).
 namespace {
 
 void plan_fp64(const int *n, int count, int cus, int *tile_x, int *tile_y, int *chunk)

@@ -127,11 +127,13 @@ def test_chosen_chunk_is_the_fastest_estimate(driver):
 # A single grid's tile: float64 takes 32x13 (12 waves) when its launch is
 # estimated to end at least 2% before that of 16x16, counting a 32x13
 # plane-step as 1.45 16x16 ones.  Measured on MI355X (us per 2-step launch,
-# 16x16 against 32x13): 256^3 236.7 / 238-240, 320^3 620 / 611, 352^3
-# 787 / 751, 384^3 943 / 845, 448^3 1547 / 1504, 512^3 2020 / 1905, 640^3
-# 4759-4936 / 4093-4372.
+# 16x16 against 32x13): 176^3 119-120 / 102-106, 200^3 194 / 170-173,
+# 256^3 236.7 / 238-240, 320^3 620 / 611, 352^3 787 / 751, 384^3 943 /
+# 845, 448^3 1547 / 1504, 512^3 2020 / 1905, 640^3 4759-4936 / 4093-4372,
+# 734^3 7547-8884 / 7518-7525.
 @pytest.mark.parametrize("n,eb,want", [
     (256, 8, (16, 16, 128)), (224, 8, (16, 16, 48)), (320, 8, (16, 16, 64)), (96, 8, (16, 16, 8)),
+    (176, 8, (32, 13, 32)), (200, 8, (32, 13, 64)), (192, 8, (16, 16, 64)), (734, 8, (16, 16, 128)),
     (352, 8, (32, 13, 128)), (384, 8, (32, 13, 96)), (448, 8, (32, 13, 96)),
     (512, 8, (32, 13, 128)), (640, 8, (32, 13, 128)), (1024, 8, (32, 13, 128)),
     (256, 4, (16, 32, 64)), (512, 4, (16, 32, 128)), (96, 4, (16, 16, 8)),
