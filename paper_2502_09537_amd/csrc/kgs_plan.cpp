@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <functional>
+#include <iterator>
 #include <queue>
 #include <vector>
 
@@ -68,9 +69,20 @@ double stream3d_launch_steps(const int *n, int count, int tile_x, int tile_y, in
 int stream3d_chunk(const int *n, int count, int tile_x, int tile_y, int cus)
 {
     static const int kChunks[] = {128, 96, 64, 48, 32, 24, 16, 12, 8};
-    int best = kChunks[0];
+    std::vector<int> cands(std::begin(kChunks), std::end(kChunks));
+    if (count == 1) {
+        // a single grid also tries its equal splits, ceil(n / k) planes
+        for (int k = 1; k <= n[0]; ++k) {
+            const int c = (n[0] + k - 1) / k;
+            if (c < 8) break;
+            if (c <= 128) cands.push_back(c);
+        }
+        std::sort(cands.begin(), cands.end(), std::greater<int>());
+        cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
+    }
+    int best = cands[0];
     double best_t = stream3d_launch_steps(n, count, tile_x, tile_y, best, cus);
-    for (int c : kChunks) {
+    for (int c : cands) {
         const double t = stream3d_launch_steps(n, count, tile_x, tile_y, c, cus);
         if (t < 0.99 * best_t) {
             best = c;
@@ -90,8 +102,10 @@ int stream3d_chunk(const int *n, int count, int tile_x, int tile_y, int cus)
 // 334^3 859-863 / 774-784, 352^3 787 / 751, 384^3 943 / 845, 448^3 1547 /
 // 1504, 512^3 2020 / 1905, 640^3 4759-4936 / 4093-4372, 734^3 7547-8884 /
 // 7518-7525.  Divided by the estimated plane-steps, a 32x13 plane-step
-// took 1.36-1.53 times a 16x16 one.  The rule keeps 16x16 at 256^3 and
-// misses only near-ties (320^3, 734^3: 32x13 faster by at most 1.5%).
+// took 1.36-1.53 times a 16x16 one.  The rule keeps 16x16 at 256^3; with
+// equal-split chunks it takes 32x13 at 320^3 (80 planes: 545-555 us
+// against 626 for 16x16 with 64) and 734^3 (105 planes: 6470-6493 against
+// 7750-7812 for 16x16 with 128).
 namespace {
 
 void plan_fp64(const int *n, int count, int cus, int *tile_x, int *tile_y, int *chunk)

@@ -15,7 +15,8 @@ int device_cus();
 double stream3d_launch_steps(const int *n, int count, int tile_x, int tile_y, int chunk, int cus);
 
 // The plane chunk (8..128) whose launch is estimated to end first, the
-// longer of two within 1%.
+// longer of two within 1%, from 128, 96, 64, 48, 32, 24, 16, 12 and 8
+// planes and, for a single grid (count 1), its equal splits ceil(n / k).
 int stream3d_chunk(const int *n, int count, int tile_x, int tile_y, int cus);
 
 // Tile and plane chunk of a four-sweep z-streaming launch over one n^3 grid

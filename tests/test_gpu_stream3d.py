@@ -126,8 +126,8 @@ def test_default_fp32_3d_tile(n, tile):
 @pytest.mark.parametrize("prec", [workloads.FP64, workloads.FP32])
 def test_default_chunk_on_a_grid_between_whole_rounds(prec):
     # at 224^3 the items of 64-plane (float64) or 32-plane (float32) chunks
-    # fill 1.5 rounds of the CUs: the default takes longer chunks with a
-    # ragged last one (96, 96, 32 / 48 x 4, 32), bitwise the same state
+    # fill 1.5 rounds of the CUs: the default takes equal splits of 45
+    # planes (4 x 45 + 44) and a ragged last one, bitwise the same state
     p = workloads.random_problem(3, 224, seed=7, tau=0.02, amp=0.5, precision=prec)
     say("default chunk 224^3", prec)
     sim = kgs.simulation_from_problem(p)
@@ -135,7 +135,7 @@ def test_default_chunk_on_a_grid_between_whole_rounds(prec):
         t = sim.tuning
     finally:
         sim.close()
-    assert t.kernel == kgs.KGS_KERNEL_STREAM and 8 <= t.chunk <= 128
+    assert t.kernel == kgs.KGS_KERNEL_STREAM and t.chunk == 45
     (a, ea) = run(p, 2)
     (b, eb) = run(p, 2, t)
     for x, y in zip(a, b):

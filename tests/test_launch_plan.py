@@ -8,7 +8,12 @@ checked against closed forms (whole rounds) and against a plain simulation
 of that rule written here, and its choices against chunks measured on
 MI355X (faster: 48 at 224^3 (1.04e11 updates/s against 9.1e10 with 64 and
 6.5e10 with 96), 64 at 320^3 and 448^3 in float64; 48 at 224^3 and 96 at
-448^3 in float32)."""
+448^3 in float32).  A single grid also tries its equal splits ceil(n / k):
+measured, us per 2-step launch, old choice against the equal split,
+float64 200^3 172 / 147-152 (32x13 tiles, 64 / 50 planes), 224^3 204 /
+197 (16x16, 48 / 45), 448^3 1502-1517 / 1412 (32x13, 96 / 112), float32
+448^3 1127-1137 / 1081-1091 (16x32, 96 / 90), 480^3 1461-1491 / 1421
+(96 / 120)."""
 import heapq
 import os
 import shutil
@@ -105,11 +110,30 @@ def test_many_items_use_work_over_cus(driver):
 
 
 @pytest.mark.parametrize("ty,n,best", [
-    (16, 256, 128), (16, 224, 48), (16, 320, 64), (16, 448, 64), (16, 128, 16), (16, 96, 8),
-    (32, 256, 64), (32, 224, 48), (32, 448, 96), (32, 512, 128),
+    (16, 256, 128), (16, 224, 45), (16, 320, 64), (16, 448, 90), (16, 128, 16), (16, 96, 8),
+    (32, 256, 64), (32, 224, 45), (32, 448, 90), (32, 512, 128),
 ])
 def test_chosen_chunks(driver, ty, n, best):
     assert driver(16, ty, 256, 0, [n])[0] == best
+
+
+SET = (128, 96, 64, 48, 32, 24, 16, 12, 8)
+
+
+@pytest.mark.parametrize("tx,ty", [(16, 16), (32, 13), (16, 32)])
+def test_single_grid_chunk_is_the_fastest_estimate(driver, tx, ty):
+    """One grid: the candidates are the fixed chunks and the equal splits
+    ceil(n / k) between 8 and 128; the pick is the longest whose estimate is
+    within 1% of every longer one's best (the plain simulation here)."""
+    for n in (98, 160, 200, 224, 254, 320, 352, 416, 448, 480):
+        cands = sorted(set(SET) | {-(-n // k) for k in range(1, n + 1) if 8 <= -(-n // k) <= 128},
+                       reverse=True)
+        best, best_t = cands[0], simulate(tx, ty, 256, cands[0], [n])
+        for c in cands:
+            t = simulate(tx, ty, 256, c, [n])
+            if t < 0.99 * best_t:
+                best, best_t = c, t
+        assert driver(tx, ty, 256, 0, [n])[0] == best, n
 
 
 def test_chosen_chunk_is_the_fastest_estimate(driver):
@@ -130,11 +154,13 @@ def test_chosen_chunk_is_the_fastest_estimate(driver):
 # 16x16 against 32x13): 176^3 119-120 / 102-106, 200^3 194 / 170-173,
 # 256^3 236.7 / 238-240, 320^3 620 / 611, 352^3 787 / 751, 384^3 943 /
 # 845, 448^3 1547 / 1504, 512^3 2020 / 1905, 640^3 4759-4936 / 4093-4372,
-# 734^3 7547-8884 / 7518-7525.
+# 734^3 7547-8884 / 7518-7525; with equal-split chunks (the rule's picks
+# here) 320^3 626 (16x16, 64 planes) against 545-555 (32x13, 80), 734^3
+# 7750-7812 (16x16, 128) against 6470-6493 (32x13, 105).
 @pytest.mark.parametrize("n,eb,want", [
-    (256, 8, (16, 16, 128)), (224, 8, (16, 16, 48)), (320, 8, (16, 16, 64)), (96, 8, (16, 16, 8)),
-    (176, 8, (32, 13, 32)), (200, 8, (32, 13, 64)), (192, 8, (16, 16, 64)), (734, 8, (16, 16, 128)),
-    (352, 8, (32, 13, 128)), (384, 8, (32, 13, 96)), (448, 8, (32, 13, 96)),
+    (256, 8, (16, 16, 128)), (224, 8, (16, 16, 45)), (320, 8, (32, 13, 80)), (96, 8, (16, 16, 8)),
+    (176, 8, (32, 13, 30)), (200, 8, (32, 13, 50)), (192, 8, (16, 16, 64)), (734, 8, (32, 13, 105)),
+    (352, 8, (32, 13, 118)), (384, 8, (32, 13, 96)), (448, 8, (32, 13, 112)), (416, 8, (16, 16, 70)),
     (512, 8, (32, 13, 128)), (640, 8, (32, 13, 128)), (1024, 8, (32, 13, 128)),
     (256, 4, (16, 32, 64)), (512, 4, (16, 32, 128)), (96, 4, (16, 16, 8)),
 ])
