@@ -48,8 +48,9 @@ struct BatchClass {
     bool s2_tile = false;
     // 3-D streaming (uniform runs of 3-D sweep classes whose members are all
     // n >= kStream3dMinN): the same descriptor triple, s2_tasks workgroups
-    // of the z-streaming kernel's member-list launch, chunk s2_chunk, tile
-    // s2_tx compressed positions x s2_ty rows
+    // of the z-streaming kernel's member-list launch, nominal chunk s2_chunk
+    // (a member of n planes takes member_chunk(n, s2_chunk)), tile s2_tx
+    // compressed positions x s2_ty rows
     bool s3 = false;
     int s2_ty = 0, s2_tx = 0;
 };
@@ -149,7 +150,7 @@ bool apply_group(kgs_batch *b, BatchClass &c, const kgs::GroupTuning &t)
         if (t.mode == kgs::GROUP_STREAM3D) {
             if (n < kStream3dMinN || !kgs::stream3d_list_ok(x->geo, t.chunk, eb, tx3, ty3))
                 return false;
-            tb += kgs::stream3d_member_items(n, t.chunk, tx3, ty3);
+            tb += kgs::stream3d_member_items(n, kgs::member_chunk(n, t.chunk), tx3, ty3);
         } else if (t.mode == kgs::GROUP_TILE2D) {
             if (!kgs::tile2d_shape_ok(x->geo, t.ty, t.tx, 4, eb)) return false;
             tb += kgs::tile2d_member_tiles(n, t.ty, t.tx);
@@ -176,12 +177,13 @@ bool apply_group(kgs_batch *b, BatchClass &c, const kgs::GroupTuning &t)
             m.task_begin = tb;
             m.k = x->coef;
             m.n = n;
-            m.chunk = c.s2_tile ? c.s2_ty : c.s2_chunk;
+            m.chunk = c.s3 ? kgs::member_chunk(n, c.s2_chunk) : c.s2_tile ? c.s2_ty : c.s2_chunk;
             m.tiles_x = c.s3 ? 0 : c.s2_tile ? kgs::tile2d_tiles_x(n, c.s2_tx)
                                              : kgs::stream2d_tiles_x(n);
             // in/out/first are set by refresh_descriptors
         }
-        tb += c.s3 ? kgs::stream3d_member_items(n, c.s2_chunk, c.s2_tx, c.s2_ty)
+        tb += c.s3 ? kgs::stream3d_member_items(n, kgs::member_chunk(n, c.s2_chunk), c.s2_tx,
+                                                c.s2_ty)
                    : c.s2_tile ? kgs::tile2d_member_tiles(n, c.s2_ty, c.s2_tx)
                                : kgs::stream2d_tasks(n, c.s2_chunk);
     }
@@ -519,7 +521,9 @@ int kgs_batch_create(kgs_sim *const *sims, int32_t count, void *stream, kgs_batc
                 int tx = 0, ty = 0, chunk = 0;
                 kgs::stream3d_list_plan(sizes.data(), static_cast<int>(nm), eb, &tx, &ty, &chunk);
                 int64_t items = 0;
-                for (size_t i = 0; i < nm; ++i) items += kgs::stream3d_member_items(sizes[i], chunk, tx, ty);
+                for (size_t i = 0; i < nm; ++i)
+                    items += kgs::stream3d_member_items(sizes[i], kgs::member_chunk(sizes[i], chunk),
+                                                        tx, ty);
                 bool ok = items <= 0x7ffffff0;  // the launch's item limit
                 for (size_t i = 0; i < nm && ok; ++i) {
                     const kgs_sim *x = b->sims[c.members[i]];

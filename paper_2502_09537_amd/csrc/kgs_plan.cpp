@@ -21,6 +21,13 @@ namespace kgs {
 // of one round of 128-plane items took 260 us, of two rounds of 64-plane
 // items 291 us (145.5 per item), which puts the fixed cost of an item
 // (pipeline fill and drain, set-up) at 17 plane-steps.
+int member_chunk(int n, int chunk)
+{
+    if (n < 1 || chunk < 1) return chunk;
+    const int k = (n + chunk - 1) / chunk;
+    return (n + k - 1) / k;
+}
+
 double stream3d_launch_steps(const int *n, int count, int tile_x, int tile_y, int chunk, int cus)
 {
     constexpr int kItemSteps = 17;
@@ -33,10 +40,11 @@ double stream3d_launch_steps(const int *n, int count, int tile_x, int tile_y, in
     for (int m = 0; m < count; ++m) {
         const int64_t tiles =
             static_cast<int64_t>((n[m] / 2 + tile_x - 1) / tile_x) * ((n[m] + tile_y - 1) / tile_y);
-        const int nc = (n[m] + chunk - 1) / chunk;
+        const int cm = member_chunk(n[m], chunk);
+        const int nc = (n[m] + cm - 1) / cm;
         items += tiles * nc;
         work += static_cast<double>(tiles) * (n[m] + static_cast<double>(nc) * kItemSteps);
-        longest = std::max(longest, std::min(chunk, n[m]) + kItemSteps);
+        longest = std::max(longest, std::min(cm, n[m]) + kItemSteps);
     }
     if (items > kDealLimit) return work / cus + longest;
     // item lengths in item order: per member its tiles first, then its chunks
@@ -45,8 +53,9 @@ double stream3d_launch_steps(const int *n, int count, int tile_x, int tile_y, in
     for (int m = 0; m < count; ++m) {
         const int64_t tiles =
             static_cast<int64_t>((n[m] / 2 + tile_x - 1) / tile_x) * ((n[m] + tile_y - 1) / tile_y);
-        for (int z0 = 0; z0 < n[m]; z0 += chunk)
-            len.insert(len.end(), static_cast<size_t>(tiles), std::min(chunk, n[m] - z0) + kItemSteps);
+        const int cm = member_chunk(n[m], chunk);
+        for (int z0 = 0; z0 < n[m]; z0 += cm)
+            len.insert(len.end(), static_cast<size_t>(tiles), std::min(cm, n[m] - z0) + kItemSteps);
     }
     const int groups = cus % kXcds == 0 ? kXcds : 1;
     const int per = cus / groups;
@@ -89,7 +98,7 @@ int stream3d_chunk(const int *n, int count, int tile_x, int tile_y, int cus)
             best_t = t;
         }
     }
-    return best;
+    return count == 1 ? member_chunk(n[0], best) : best;
 }
 
 // The float64 pipeline holds 162 VGPRs per thread at run-time tile shapes,

@@ -9,14 +9,21 @@ namespace kgs {
 // is visible), cached per device.
 int device_cus();
 
+// Planes per chunk of an n-plane grid in a launch of nominal plane chunk
+// `chunk`: the equal split into as many chunks, ceil(n / ceil(n / chunk)),
+// so that no chunk of a grid is much shorter than its others.
+int member_chunk(int n, int chunk);
+
 // Estimated duration, in plane-steps, of a four-sweep z-streaming launch
-// over grids n[0..count) with the tile_x x tile_y tile and plane chunk
-// `chunk` on a device of `cus` compute units (one workgroup per CU).
+// over grids n[0..count) with the tile_x x tile_y tile and nominal plane
+// chunk `chunk` (member_chunk for each grid) on a device of `cus` compute
+// units (one workgroup per CU).
 double stream3d_launch_steps(const int *n, int count, int tile_x, int tile_y, int chunk, int cus);
 
-// The plane chunk (8..128) whose launch is estimated to end first, the
-// longer of two within 1%, from 128, 96, 64, 48, 32, 24, 16, 12 and 8
-// planes and, for a single grid (count 1), its equal splits ceil(n / k).
+// The nominal plane chunk (8..128) whose launch is estimated to end
+// first, the longer of two within 1%, from 128, 96, 64, 48, 32, 24, 16, 12
+// and 8 planes and, for a single grid (count 1), its equal splits
+// ceil(n / k); for a single grid the result is its member_chunk.
 int stream3d_chunk(const int *n, int count, int tile_x, int tile_y, int cus);
 
 // Tile and plane chunk of a four-sweep z-streaming launch over one n^3 grid

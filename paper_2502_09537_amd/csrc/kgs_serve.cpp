@@ -903,10 +903,10 @@ int run_stream3d(kgs_server *s, int prec, int64_t k, const std::vector<Request *
             m.task_begin = tb;
             m.k = x->coef;
             m.n = x->geo.n;
-            m.chunk = chunk;
+            m.chunk = kgs::member_chunk(x->geo.n, chunk);
             m.first = v == 0 ? 1 : 0;
         }
-        tb += kgs::stream3d_member_items(x->geo.n, chunk, tx, ty);
+        tb += kgs::stream3d_member_items(x->geo.n, kgs::member_chunk(x->geo.n, chunk), tx, ty);
         std::memset(&bm[i], 0, sizeof(bm[i]));
         bm[i].state = x->state;
         bm[i].stride = x->geo.stride;

@@ -56,13 +56,20 @@ def driver(tmp_path_factory):
     return run
 
 
+def member_chunk(n, chunk):
+    """A grid's planes per chunk: the equal split into as many chunks."""
+    k = -(-n // chunk)
+    return -(-n // k)
+
+
 def simulate(tx, ty, cus, chunk, sizes):
-    """The dealing rule, item by item."""
+    """The dealing rule, item by item (each grid with its member_chunk)."""
     lens = []
     for n in sizes:
         tiles = ((n // 2 + tx - 1) // tx) * ((n + ty - 1) // ty)
-        for z0 in range(0, n, chunk):
-            lens += [min(chunk, n - z0) + ITEM] * tiles
+        cm = member_chunk(n, chunk)
+        for z0 in range(0, n, cm):
+            lens += [min(cm, n - z0) + ITEM] * tiles
     items = len(lens)
     groups = 8 if cus % 8 == 0 else 1
     per = cus // groups
@@ -101,6 +108,16 @@ def test_estimate_equals_plain_simulation(driver, tx, ty, cus, chunk, sizes):
     assert driver(tx, ty, cus, chunk, sizes)[1] == simulate(tx, ty, cus, chunk, sizes)
 
 
+def test_member_chunk_is_the_equal_split():
+    # the same number of chunks as the nominal chunk gives, none shorter
+    # than the others by more than one plane
+    for n in range(2, 600, 3):
+        for c in (8, 12, 16, 24, 32, 48, 64, 96, 128):
+            m = member_chunk(n, c)
+            k = -(-n // c)
+            assert m <= c and -(-n // m) == k and n - (k - 1) * m >= m - k
+
+
 def test_many_items_use_work_over_cus(driver):
     # beyond 16384 items: total steps over the CUs plus one item
     n = 1024
@@ -133,7 +150,7 @@ def test_single_grid_chunk_is_the_fastest_estimate(driver, tx, ty):
             t = simulate(tx, ty, 256, c, [n])
             if t < 0.99 * best_t:
                 best, best_t = c, t
-        assert driver(tx, ty, 256, 0, [n])[0] == best, n
+        assert driver(tx, ty, 256, 0, [n])[0] == member_chunk(n, best), n
 
 
 def test_chosen_chunk_is_the_fastest_estimate(driver):
