@@ -24,6 +24,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2502_09537_amd", "csrc")
 ITEM = 17
+SET = (128, 96, 64, 48, 32, 24, 16, 12, 8)  # the planner's fixed plane chunks
 
 
 @pytest.fixture(scope="module")
@@ -134,8 +135,6 @@ def test_chosen_chunks(driver, ty, n, best):
     assert driver(16, ty, 256, 0, [n])[0] == best
 
 
-SET = (128, 96, 64, 48, 32, 24, 16, 12, 8)
-
 
 @pytest.mark.parametrize("tx,ty", [(16, 16), (32, 13), (16, 32)])
 def test_single_grid_chunk_is_the_fastest_estimate(driver, tx, ty):
@@ -143,21 +142,32 @@ def test_single_grid_chunk_is_the_fastest_estimate(driver, tx, ty):
     ceil(n / k) between 8 and 128; the pick is the longest whose estimate is
     within 1% of every longer one's best (the plain simulation here)."""
     for n in (98, 160, 200, 224, 254, 320, 352, 416, 448, 480):
-        cands = sorted(set(SET) | {-(-n // k) for k in range(1, n + 1) if 8 <= -(-n // k) <= 128},
-                       reverse=True)
-        best, best_t = cands[0], simulate(tx, ty, 256, cands[0], [n])
-        for c in cands:
-            t = simulate(tx, ty, 256, c, [n])
-            if t < 0.99 * best_t:
-                best, best_t = c, t
-        assert driver(tx, ty, 256, 0, [n])[0] == member_chunk(n, best), n
+        assert driver(tx, ty, 256, 0, [n])[0] == planned_chunk(tx, ty, 256, [n]), n
+
+
+def planned_chunk(tx, ty, cus, sizes):
+    """The planner's rule written out: candidates are the fixed chunks and,
+    for a single grid, its equal splits ceil(n / k), between 8 and 128,
+    scanned from the longest; a shorter one wins only by more than 1%."""
+    cands = set(SET)
+    if len(sizes) == 1:
+        n = sizes[0]
+        cands |= {-(-n // k) for k in range(1, n + 1) if 8 <= -(-n // k) <= 128}
+    cands = sorted(cands, reverse=True)
+    best, best_t = cands[0], simulate(tx, ty, cus, cands[0], sizes)
+    for c in cands:
+        t = simulate(tx, ty, cus, c, sizes)
+        if t < 0.99 * best_t:
+            best, best_t = c, t
+    return member_chunk(sizes[0], best) if len(sizes) == 1 else best
 
 
 def test_chosen_chunk_is_the_fastest_estimate(driver):
     sizes = [64, 96, 128, 160, 192, 224, 256, 130, 200, 98]
     best = driver(16, 16, 256, 0, sizes)[0]
-    est = {c: simulate(16, 16, 256, c, sizes) for c in (128, 96, 64, 48, 32, 24, 16, 12, 8)}
-    assert est[best] <= min(est.values()) / 0.99
+    assert best == planned_chunk(16, 16, 256, sizes)
+    fixed = min(simulate(16, 16, 256, c, sizes) for c in SET)
+    assert simulate(16, 16, 256, best, sizes) <= fixed / 0.99
     # list launches: float32 with its list tile (16x32), float64 with the
     # single-grid tile rule over the whole list
     _, _, l64, l32 = driver(16, 16, 256, 0, sizes)
