@@ -145,12 +145,14 @@ def test_default_chunk_on_a_grid_between_whole_rounds(prec):
 
 def test_default_fp64_wide_tile_at_full_size_equals_sweep():
     """At 384^3 the float64 default is the 12-wave 32x13 tile with 96-plane
-    chunks (180 tiles x 4 chunks); two steps give bitwise the state of the
-    colour sweeps.  At 256^3 the default stays 16x16 x 128 planes."""
+    chunks (180 tiles x 4 chunks), at 200^3 the same tile with the equal
+    split of 50 planes (4 x 16 tiles x 4 chunks); two steps give bitwise the
+    state of the colour sweeps.  At 256^3 the default stays 16x16 x 128
+    planes."""
     import torch
 
-    say("float64 default tile 256^3 / 384^3")
-    for n, want in ((256, (16, 16, 128)), (384, (32, 13, 96))):
+    say("float64 default tile 256^3 / 384^3 / 200^3")
+    for n, want in ((256, (16, 16, 128)), (384, (32, 13, 96)), (200, (32, 13, 50))):
         cfg = kgs.make_config(3, n, -8.0, 8.0, 0.002)
         f = workloads.random_fields_torch(3, n, seed=29)
         psi = torch.complex(f[0], f[1])
@@ -168,7 +170,7 @@ def test_default_fp64_wide_tile_at_full_size_equals_sweep():
                 states.append(sim.read_state(as_torch=True))
             finally:
                 sim.close()
-        if n == 384:
+        if n != 256:
             for x, y in zip(*states):
                 assert torch.equal(x, y)
         del f, psi, states
