@@ -164,12 +164,13 @@ kgs::Geometry make_geometry(const kgs_config &c)
 //  * 2-D float32 grids from n = 2048: the y-streaming kernel, 2 steps per
 //    launch, the longest row chunk (8..64) that still gives 8192 waves;
 //  * 3-D grids with n >= 96: the z-streaming kernel with two steps per
-//    launch, 16x16 tiles in float64 and, from n = 128, 16x32 tiles in
-//    float32 (13 waves per workgroup: 17-24% faster than 16x16 at
-//    n = 192..512, 3-6% at 128, 30% slower at 96 where 16x32 tiles leave
-//    most CUs idle), the chunk of z-planes (8..128) that stream3d_chunk
+//    launch and the tile and chunk of z-planes (8..128) that stream3d_plan
 //    estimates to end the launch first on this device (the CUs take one
-//    workgroup each, so the items should fill whole rounds of them);
+//    workgroup each, so the items should fill whole rounds of them):
+//    float64 16x16 tiles or, where they end sooner, 12-wave 32x13 tiles;
+//    float32 16x32 tiles from n = 128 (13 waves per workgroup: 17-24%
+//    faster than 16x16 at n = 192..512, 3-6% at 128, 30% slower at 96
+//    where 16x32 tiles leave most CUs idle);
 //  * one colour sweep per launch otherwise (3-D below n = 96, 1-D grids
 //    beyond the resident kernel).
 kgs_tuning default_tuning(const kgs_config &c, bool with_chunk = true)
